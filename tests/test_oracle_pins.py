@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each test anchors one oracle function to something other than itself: a
+published known-answer vector, a closed form, an independent brute-force
+construction, an exact invariant or a library routine it reduces to.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import philox, circuit, dense, mps, sample, precision, mlp, rsvd
+from oracle.circuit import Circuit, SQRT_X, SQRT_Y, SQRT_W, SWAP, fsim
+from tests import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+X = np.array([[0, 1], [1, 0]], dtype=complex)
+Y = np.array([[0, -1j], [1j, 0]], dtype=complex)
+WP = (X + Y) / math.sqrt(2)
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLD, "philox_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = philox.philox4x32_10(*v[:4], v[4], v[5])
+        assert [int(o) for o in out] == v[6:]
+
+
+def test_u53_range_and_resolution():
+    assert philox.u53(0, 0) == 0.0
+    assert philox.u53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    # the low 11 bits of the 64-bit word are dropped
+    assert philox.u53(0x7FF, 0) == 0.0 and philox.u53(0x800, 0) == 2.0 ** -53
+
+
+def test_shot_uniform_word_selection():
+    k0, k1 = philox.key_of(1234)
+    x = philox.philox4x32_10(7, 0, 2, philox.STREAM_SHOTS, k0, k1)
+    assert philox.shot_uniform(1234, 7, 4) == philox.u53(x[0], x[1])
+    assert philox.shot_uniform(1234, 7, 5) == philox.u53(x[2], x[3])
+
+
+# ------------------------------------------------------------------- gates
+@pytest.mark.parametrize("U,P", [(SQRT_X, X), (SQRT_Y, Y), (SQRT_W, WP)])
+def test_sqrt_gates(U, P):
+    assert np.abs(U.conj().T @ U - np.eye(2)).max() < 1e-15
+    assert np.abs(U @ U - P).max() < 1e-15          # principal square root
+    assert abs(abs(U[0, 0]) ** 2 - 0.5) < 1e-15
+
+
+def test_fsim_identities():
+    phi = math.pi / 6
+    G = fsim(math.pi / 2, phi)
+    assert np.abs(G.conj().T @ G - np.eye(4)).max() < 1e-15
+    D = np.diag([1, -1j, -1j, np.exp(-1j * phi)])
+    assert np.abs(G @ SWAP - D).max() < 1e-15
+    assert np.abs(SWAP @ G - D).max() < 1e-15
+
+    def op_schmidt_rank(g):
+        t = g.reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(4, 4)
+        return int(np.sum(np.linalg.svd(t, compute_uv=False) > 1e-12))
+    assert op_schmidt_rank(G) == 4
+    assert op_schmidt_rank(SWAP @ G) == 2
+    assert op_schmidt_rank(SWAP) == 4
+    # fSim is symmetric under exchanging the qubits
+    assert np.abs(SWAP @ G @ SWAP - G).max() < 1e-15
+
+
+# ---------------------------------------------------------------- circuits
+def test_generator_rules():
+    c = Circuit(6, 9, 20, seed=99, n_removed_random=1)
+    assert c.n == 53 and c.W == 6 and c.H == 9 and len(c.removed) == 1
+    draws = c.one_qubit_draws()
+    assert draws.shape == (21, 53)
+    assert np.all(draws[1:] != draws[:-1])            # never repeats
+    assert set(np.unique(draws)) == {0, 1, 2}
+    for letter in "ABCD":
+        cp = c.couplers(letter)
+        qs = [q for e in cp for q in e]
+        assert len(qs) == len(set(qs))                # a matching
+    full = Circuit(6, 9, 1, seed=1)
+    assert [len(full.couplers(l)) for l in "ABCD"] == [27, 18, 24, 24]
+    # pattern order ABCDCDAB
+    seq = [len(d) for k, d in Circuit(3, 4, 8, seed=3).layers if k == "2q"]
+    ref = Circuit(3, 4, 1, seed=3)
+    assert seq == [len(ref.couplers(l)) for l in "ABCDCDAB"]
+
+
+def test_removed_site_follows_layout_stream():
+    c = Circuit(6, 9, 2, seed=5, n_removed_random=1)
+    x0 = philox.philox4x32_10(0, 0, 0, 1, 5, 0)[0]
+    assert c.removed == [int(x0) % 54]
+
+
+def test_first_draw_is_uniform_over_three():
+    c = Circuit(20, 20, 1, seed=11)
+    g = c.one_qubit_draws()[0]
+    counts = np.bincount(g, minlength=3)
+    assert counts.min() > 400 / 3 - 4 * math.sqrt(400 * 2 / 9)
+
+
+# ------------------------------------------------------------------- dense
+def _kron_unitary(circ):
+    """Brute force: the full 2^n x 2^n unitary as a product of Kronecker
+    products (qubit q is the 2^q place value, so it is the q-th factor from
+    the right)."""
+    n = circ.n
+    total = np.eye(1 << n, dtype=complex)
+    gates = circuit.ONE_QUBIT_GATES
+
+    def embed1(U, q):
+        mats = [np.eye(2)] * n
+        mats[n - 1 - q] = U
+        out = np.array([[1.0 + 0j]])
+        for m_ in mats:
+            out = np.kron(out, m_)
+        return out
+
+    def embed2(G, qa, qb):
+        dim = 1 << n
+        out = np.zeros((dim, dim), dtype=complex)
+        for i in range(dim):
+            sa, sb = (i >> qa) & 1, (i >> qb) & 1
+            for ta in range(2):
+                for tb in range(2):
+                    j = i & ~(1 << qa) & ~(1 << qb) | (ta << qa) | (tb << qb)
+                    out[j, i] += G[2 * ta + tb, 2 * sa + sb]
+        return out
+
+    for kind, data in circ.layers:
+        if kind == "1q":
+            for q in range(n):
+                total = embed1(gates[int(data[q])], q) @ total
+        else:
+            for qa, qb in data:
+                total = embed2(circ.gate2, qa, qb) @ total
+    return total
+
+
+@pytest.mark.parametrize("rows,cols,cyc,seed", [(2, 3, 4, 1), (2, 2, 8, 7), (3, 2, 5, 3)])
+def test_dense_equals_kronecker_brute_force(rows, cols, cyc, seed):
+    c = Circuit(rows, cols, cyc, seed=seed)
+    psi = dense.simulate(c)
+    ref = _kron_unitary(c)[:, 0]
+    assert np.abs(psi - ref).max() < 1e-13
+
+
+def test_first_layer_is_uniform_and_norm_kept():
+    c = Circuit(3, 4, 8, seed=2)
+    p = dense.probabilities(dense.simulate(c, max_layers=1))
+    assert np.abs(p - 2.0 ** -12).max() < 1e-15
+    psi = dense.simulate(c)
+    assert abs(np.vdot(psi, psi).real - 1) < 1e-12
+
+
+def test_product_distribution_without_two_qubit_layers():
+    c = Circuit(2, 3, 3, seed=4, pattern="A")
+    c.layers = [l for l in c.layers if l[0] == "1q"]
+    p = dense.probabilities(dense.simulate(c))
+    per_q = []
+    for q in range(c.n):
+        v = np.array([1, 0], dtype=complex)
+        for kind, g in c.layers:
+            v = circuit.ONE_QUBIT_GATES[int(g[q])] @ v
+        per_q.append(np.abs(v) ** 2)
+    for i in range(1 << c.n):
+        ref = np.prod([per_q[q][(i >> q) & 1] for q in range(c.n)])
+        assert abs(p[i] - ref) < 1e-15
+
+
+def test_porter_thomas_n12():
+    m2 = []
+    for seed in range(1, 17):
+        p = dense.probabilities(dense.simulate(Circuit(3, 4, 8, seed=seed)))
+        x = (2 ** 12) * p
+        assert abs(x.mean() - 1) < 1e-12
+        m2.append(np.mean(x * x))
+        assert 1.7 <= m2[-1] <= 2.5
+        xs = np.sort(x)
+        ks = np.max(np.abs(np.arange(1, len(xs) + 1) / len(xs) - (1 - np.exp(-xs))))
+        assert ks <= 0.05
+    assert 1.9 <= np.mean(m2) <= 2.2
+
+
+def test_porter_thomas_n20():
+    p = dense.probabilities(dense.simulate(Circuit(4, 5, 14, seed=1)))
+    x = (2 ** 20) * p
+    assert abs(np.mean(x * x) - 2.0) <= 0.02
+
+
+# --------------------------------------------------------------------- MPS
+@pytest.mark.parametrize("rows,cols,cyc,seed,chi", [(3, 4, 8, 1, 64), (3, 4, 8, 5, 64),
+                                                    (4, 4, 6, 2, 256), (3, 5, 10, 3, 128)])
+def test_exact_mps_equals_dense(rows, cols, cyc, seed, chi):
+    c = Circuit(rows, cols, cyc, seed=seed)
+    st = mps.build(c, chi, 0.0)
+    psi = dense.simulate(c)
+    assert np.abs(st.to_dense() - psi).max() <= 1e-12 * 2.0 ** (-c.n / 2)
+    assert st.canonical_residual() <= 1e-12
+    assert st.log_fest == 0.0
+    bits = np.arange(1 << c.n, dtype=np.uint64)
+    assert np.abs(st.amplitudes(bits) - psi).max() < 1e-13
+
+
+def test_removed_site_mps_equals_dense():
+    c = Circuit(3, 4, 6, seed=8, n_removed_random=1)
+    assert c.n == 11
+    st = mps.build(c, 64, 0.0)
+    assert np.abs(st.to_dense() - dense.simulate(c)).max() < 1e-13
+
+
+def test_single_truncation_fidelity_is_one_minus_eps():
+    c = Circuit(3, 4, 8, seed=3)
+    psi = dense.simulate(c)
+    pi, ops = mps.schedule(c)
+    # build exactly, then truncate one central bond with a tight cap
+    st = mps.build(c, 64, 0.0)
+    st.move_center(5, 6)
+    M, cl, cr = st.two_site_matrix(5, np.eye(4))
+    s = np.linalg.svd(M, compute_uv=False)
+    k_cap = 10
+    k, eps_step = st.update(5, np.eye(4), k_cap, 0.0)
+    assert k == k_cap
+    st.right_canonicalize()
+    ov = abs(np.vdot(psi, st.to_dense())) ** 2
+    assert abs(ov - (1 - eps_step)) < 1e-12
+    # Eckart-Young: the discarded weight is the squared tail
+    assert abs(eps_step - np.sum(s[k:] ** 2) / np.sum(s ** 2)) < 1e-14
+
+
+def test_rank_rule_cases():
+    s = np.array([3.0, 2.0, 1.0, 1e-3, 1e-13])
+    w = np.sum(s ** 2)
+    k, e, _, _ = mps.rank_rule(s, 10, 0.0)
+    assert k == 4 and e == 0.0               # 1e-26 <= 1e-24 w counts as zero
+    k, e, _, _ = mps.rank_rule(s, 10, 1e-7)
+    assert k == 3 and abs(e - 1e-6 / w) < 1e-20
+    k, e, _, _ = mps.rank_rule(s, 2, 0.0)
+    assert k == 2 and abs(e - (1.0 + 1e-6) / w) < 1e-16
+    k, e, _, _ = mps.rank_rule(s, 10, 0.5)
+    assert k == 1
+
+
+def test_truncated_fest_tracks_true_fidelity():
+    c = Circuit(4, 4, 10, seed=6)
+    psi = dense.simulate(c)
+    for chi in (8, 16):
+        st = mps.build(c, chi, 1e-10)
+        f_true = abs(np.vdot(psi, st.to_dense())) ** 2
+        f_est = sample.fidelity_estimate(st.log_fest)
+        assert f_est < 1.0 and f_true < 1.0
+        assert abs(f_true - f_est) / f_est < 0.5
+
+
+# ----------------------------------------------------------------- sampler
+def _dense_sequential_sampler(psi, n, order, seed, n_shots):
+    """Independent sampler: marginals summed from the dense distribution."""
+    p = dense.probabilities(psi)
+    idx = np.arange(1 << n)
+    out = []
+    for i in range(n_shots):
+        mask = np.ones(1 << n, dtype=bool)
+        b = 0
+        for k, q in enumerate(order):
+            sel0 = mask & (((idx >> q) & 1) == 0)
+            sel1 = mask & (((idx >> q) & 1) == 1)
+            p0, p1 = p[sel0].sum(), p[sel1].sum()
+            u = philox.shot_uniform(seed, i, k)
+            s = 0 if u * (p0 + p1) < p0 else 1
+            mask = sel1 if s else sel0
+            b |= s << q
+        out.append(b)
+    return np.array(out, dtype=np.uint64)
+
+
+def test_sampler_matches_dense_marginal_sampler():
+    c = Circuit(3, 3, 6, seed=12)
+    st = mps.build(c, 64, 0.0)
+    bits, log2p, tight = sample.sample(st, 200, seed=77)
+    ref = _dense_sequential_sampler(dense.simulate(c), c.n, st.pi, 77, 200)
+    assert np.all((bits == ref) | (tight >= 0))
+    assert np.sum(tight >= 0) == 0
+    p = dense.probabilities(dense.simulate(c))[bits.astype(np.int64)]
+    assert np.abs(log2p - np.log2(p)).max() < 1e-12
+
+
+def test_sampler_ghz():
+    n = 6
+    A = []
+    for k in range(n):
+        if k == 0:
+            a = np.zeros((1, 2, 2), dtype=complex); a[0, 0, 0] = a[0, 1, 1] = 1 / math.sqrt(2)
+        elif k == n - 1:
+            a = np.zeros((2, 2, 1), dtype=complex); a[0, 0, 0] = a[1, 1, 0] = 1
+        else:
+            a = np.zeros((2, 2, 2), dtype=complex); a[0, 0, 0] = a[1, 1, 1] = 1
+        A.append(a)
+    st = mps.MPS(n, list(range(n)))
+    st.A = A
+    bits, log2p, _ = sample.sample(st, 500, seed=5)
+    u0 = philox.shot_uniform(5, np.arange(500, dtype=np.uint64), 0)
+    assert np.all(bits == np.where(u0 < 0.5, 0, (1 << n) - 1).astype(np.uint64))
+    assert np.abs(log2p + 1).max() < 1e-14
+
+
+def test_sampler_product_state_bernoulli():
+    n = 5
+    probs1 = np.array([0.1, 0.3, 0.5, 0.7, 0.9])
+    st = mps.MPS(n, [4, 0, 3, 1, 2])
+    for k in range(n):
+        q = st.pi[k]
+        a = np.zeros((1, 2, 1), dtype=complex)
+        a[0, 0, 0] = math.sqrt(1 - probs1[q]); a[0, 1, 0] = 1j * math.sqrt(probs1[q])
+        st.A[k] = a
+    bits, _, _ = sample.sample(st, 20000, seed=9)
+    for q in range(n):
+        f = np.mean((bits >> np.uint64(q)) & np.uint64(1))
+        assert abs(f - probs1[q]) < 4 * math.sqrt(probs1[q] * (1 - probs1[q]) / 20000)
+
+
+def test_sampler_goodness_of_fit_c1():
+    c = Circuit(3, 4, 8, seed=1)
+    st = mps.build(c, 64, 0.0)
+    p = dense.probabilities(dense.simulate(c))
+    bits, _, _ = sample.sample(st, 10000, seed=1001)
+    # 20 bins equiprobable under p: sort outcomes by p, cut cumulative mass
+    order = np.argsort(p)
+    cum = np.cumsum(p[order])
+    bin_of = np.empty(len(p), dtype=int)
+    bin_of[order] = np.minimum((cum * 20).astype(int), 19)
+    expect = np.array([p[bin_of == b].sum() for b in range(20)]) * 10000
+    obs = np.bincount(bin_of[bits.astype(np.int64)], minlength=20)
+    chi2 = np.sum((obs - expect) ** 2 / expect)
+    assert chi2 < 43.8          # chi-square, 19 dof, p = 0.001
+
+
+# --------------------------------------------------------------------- XEB
+def test_xeb_exact_samples_and_uniform():
+    c = Circuit(3, 4, 8, seed=4)
+    st = mps.build(c, 64, 0.0)
+    p = dense.probabilities(dense.simulate(c))
+    bits, _, _ = sample.sample(st, 20000, seed=3)
+    f, se = sample.linear_xeb(c.n, p[bits.astype(np.int64)])
+    assert abs(f - ((2 ** c.n) * np.sum(p * p) - 1)) < 4 * se
+    ub = inputs.random_bitstrings(c.n, 20000, seed=8)
+    f0, se0 = sample.linear_xeb(c.n, p[ub.astype(np.int64)])
+    assert abs(f0) < 4 * se0
+    # closed form of the estimator on a fixed sample
+    x = (2 ** c.n) * p[bits.astype(np.int64)]
+    assert f == pytest.approx(x.sum() / len(x) - 1, abs=1e-12)
+
+
+# --------------------------------------------------------------- precision
+def test_bf16_emulation_matches_torch_rounding():
+    torch = pytest.importorskip("torch")
+    x = np.concatenate([inputs.random_complex(4096, 3).real.astype(np.float32),
+                        np.array([1.0, 1.00390625, 1.01171875, -3.0, 1e-30, 65504.0],
+                                 dtype=np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(precision.bf16_rne(x), ref)
+
+
+def test_split_bf16_product_error_bound():
+    a = inputs.random_complex((64, 96), 1)
+    b = inputs.random_complex((96, 80), 2)
+    exact = a.astype(np.complex64).astype(complex) @ b.astype(np.complex64).astype(complex)
+    got = precision.matmul_split_bf16_complex(a, b)
+    rel = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+    assert rel < 2.0 ** -14
+    # dropping the cross terms (plain bf16) is far worse: the split matters
+    ah, bh = precision.bf16_rne(a.real.astype(np.float32)), precision.bf16_rne(b.real.astype(np.float32))
+    rel_plain = np.linalg.norm(ah.astype(float) @ bh.astype(float) - a.real.astype(np.float32).astype(float) @ b.real.astype(np.float32).astype(float)) \
+        / np.linalg.norm(a.real @ b.real)
+    assert rel_plain > 50 * rel
+
+
+# --------------------------------------------------------------------- MLP
+def test_mlp_backward_matches_finite_differences():
+    flat = inputs.mlp_init(3)
+    g = inputs.rng(4)
+    x = g.standard_normal((7, 66))
+    y = g.standard_normal((7, 32))
+    p = mlp.unpack(flat)
+    grad = mlp.pack(mlp.backward(p, x, y))
+    h = 1e-6
+    idx = np.concatenate([np.arange(0, 20), g.integers(0, len(flat), 60),
+                          np.arange(len(flat) - 40, len(flat))])
+    for i in idx:
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h; fm[i] -= h
+        fd = (mlp.loss(mlp.unpack(fp), x, y) - mlp.loss(mlp.unpack(fm), x, y)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-7 * max(1.0, abs(fd))
+    assert mlp.n_params() == 66 * 128 + 128 + 128 * 128 + 128 + 128 * 32 + 32
+
+
+def test_adam_first_step_closed_form():
+    g = inputs.rng(5).standard_normal(100)
+    th = inputs.rng(6).standard_normal(100)
+    new, m, v = mlp.adam_step(th, g, np.zeros(100), np.zeros(100), 1)
+    assert np.allclose(new, th - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_features_and_targets():
+    s = np.array([1.0, 0.1, 0.01, 0.0])
+    h = mlp.spectrum_histogram(s[:3])
+    # log10 of normalised squares: -0.0043, -2.0043, -4.0043 -> bins 63, 55, 47
+    assert h[63] == h[55] == h[47] == pytest.approx(1 / 3) and h.sum() == pytest.approx(1)
+    y = mlp.targets(s)
+    w = 1.0101
+    assert y[7] == pytest.approx(math.log10((0.01 + 1e-4) / w))     # f = 8/32 -> k = 1
+    assert y[-1] == -20.0
+    assert mlp.predict_rank(y, 4, 64, 1e-3) >= 2
+
+
+# -------------------------------------------------------------------- RSVD
+def test_rsvd_exact_when_sketch_covers_rank():
+    M = inputs.planted_matrix(40, 30, np.linspace(2, 0.5, 12), seed=1)
+    U, s, Vh = rsvd.rsvd(M, 16, 1, seed=3, step=0)
+    s_full = np.linalg.svd(M, compute_uv=False)
+    assert np.abs(s[:12] - s_full[:12]).max() < 1e-12
+    assert np.linalg.norm(U[:, :12] * s[:12] @ Vh[:12] - M) < 1e-12
+
+
+def test_rsvd_interlacing_and_hmt_bound():
+    spec = 0.9 ** np.arange(60)
+    M = inputs.planted_matrix(80, 70, spec, seed=2)
+    k, p, q = 10, 6, 1
+    U, s, Vh = rsvd.rsvd(M, k + p, q, seed=4, step=1)
+    s_full = np.linalg.svd(M, compute_uv=False)
+    assert np.all(s <= s_full[:len(s)] + 1e-12)
+    fro2 = np.sum(s_full ** 2)
+    _, e_rand = rsvd.rsvd_rank(s, fro2, k, 0.0)
+    e_full = np.sum(s_full[k:] ** 2) / fro2
+    assert e_rand >= e_full - 1e-15
+    # HMT (Thm 10.5 / 10.6 style) expected-error bound, generous constant
+    err = np.linalg.norm(M - (U[:, :k] * s[:k]) @ Vh[:k], 2)
+    bound = (1 + 9 * math.sqrt(k + p) * math.sqrt(min(M.shape))) ** (1 / (2 * q + 1)) * s_full[k]
+    assert err <= bound
+
+
+def test_sketch_entries_are_unit_phases():
+    om = rsvd.sketch(50, 20, seed=9, step=3)
+    assert np.all(np.isin(np.round(om, 12), [1, 1j, -1, -1j]))
+    k0, k1 = philox.key_of(9)
+    x0 = philox.philox4x32_10(17, 5, 3, 4, k0, k1)[0]
+    assert om[17, 5] == [1, 1j, -1, -1j][int(x0) & 3]
