@@ -1,0 +1,276 @@
+/*
+ * rcs.h -- C ABI of librcs: build the output state of a Sycamore-style grid
+ * random circuit as a matrix-product state on one MI355X (gfx950), draw
+ * bitstring shots from it, evaluate amplitudes, and score shots by linear
+ * cross-entropy benchmarking (XEB).
+ *
+ * The paper's pipeline (Section 3.2) has four stages: state construction on
+ * one GPU, persistence, distributed measurement sampling, and post-processing
+ * that computes the linear XEB score (Section 5.1).  This library is the
+ * data-parallel core of stages 1, 3 and 4 on one device; the state
+ * representation (snake-ordered MPS with SVD truncation) is this library's
+ * own choice since the paper does not describe its engine.
+ *
+ * Conventions for every entry point
+ *  - Return value: RCS_OK (0) on success, another rcs_status on failure.  On
+ *    failure nothing is written to outputs, handle outputs stay NULL, and
+ *    rcs_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses the ABI.
+ *  - Bitstrings are uint64 with bit q = measured value of qubit q; qubits are
+ *    the present grid sites numbered in row-major order (n <= 64).
+ *  - Pointers named *_dev are device pointers owned by the caller (e.g. the
+ *    storage of a torch tensor on the same device).  Work on them is ordered
+ *    on the state's stream (rcs_build_opts.stream, or rcs_state_set_stream).
+ *    Calls that return host scalars synchronise that stream.
+ *  - Pointers named *_host are host memory owned by the caller.
+ *  - Handles are not thread-safe: one call at a time per handle.
+ *  - Complex numbers are two consecutive doubles (re, im), i.e. the layout of
+ *    C99 double _Complex and numpy complex128.
+ */
+#ifndef RCS_H
+#define RCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rcs_circuit_s* rcs_circuit;
+typedef struct rcs_state_s* rcs_state;
+
+typedef enum {
+  RCS_OK = 0,
+  RCS_ERR_INVALID_ARG = 1,
+  RCS_ERR_UNSUPPORTED = 2,
+  RCS_ERR_OUT_OF_MEMORY = 3,
+  RCS_ERR_DEVICE = 4,
+  RCS_ERR_NUMERIC = 5, /* NaN/Inf, or an SVD that did not converge */
+  RCS_ERR_STATE = 6    /* handle in the wrong state for the call */
+} rcs_status;
+
+/* ------------------------------------------------------------------ circuits
+ * Section 3.1: 53-qubit random circuits, single-qubit gates drawn from
+ * {sqrt(X), sqrt(Y), sqrt(W)}, fSim two-qubit gates on coupler pattern
+ * sequence ABCDCDAB.  Generated here on a rectangular grid:
+ *   W = min(rows, cols) columns, H = max(rows, cols) rows, site r*W + c;
+ *   pattern A = horizontal couplers (r,c)-(r,c+1) with c even, B with c odd,
+ *   C = vertical (r,c)-(r+1,c) with r even, D with r odd;
+ *   cycle t: one single-qubit gate per qubit (never the previous one on that
+ *   qubit), then fSim(theta, phi) on every coupler of pattern[t mod len];
+ *   optional final single-qubit layer.
+ * All draws come from Philox4x32-10 keyed by the seed (counter layout in
+ * the library's design notes); the same desc always gives the same circuit.
+ */
+typedef struct {
+  int32_t rows, cols;             /* grid, 2 <= rows, cols; rows*cols <= 4096 */
+  int32_t n_cycles;               /* >= 0 */
+  uint64_t seed;
+  int32_t n_removed;              /* explicit absent sites ...               */
+  const int32_t* removed_sites;   /* ... site indices r*W + c (host, nullable) */
+  int32_t n_removed_random;       /* 0 or 1 extra seed-chosen absent site     */
+  const char* pattern;            /* letters from "ABCD"; NULL -> "ABCDCDAB"  */
+  double theta, phi;              /* fSim angles (pi/2, pi/6 for Sycamore)    */
+  int32_t final_1q_layer;         /* 1: one more single-qubit layer at end    */
+} rcs_circuit_desc;
+
+/* Validates and generates the circuit and its MPS schedule (host only, no
+ * device work).  Errors: INVALID_ARG for null pointers, a grid below 2x2,
+ * more than 64 present qubits, bad pattern letters or out-of-range sites. */
+rcs_status rcs_circuit_create(const rcs_circuit_desc* desc, rcs_circuit* out);
+void rcs_circuit_destroy(rcs_circuit c);
+
+/* Sizes: qubits, single-qubit layers, schedule ops, two-site updates
+ * (gates plus SWAPs of the swap network).  Any output may be NULL. */
+rcs_status rcs_circuit_info(rcs_circuit c, int32_t* n_qubits, int32_t* n_layers_1q,
+                            int32_t* n_ops, int32_t* n_updates);
+
+/* Single-qubit gate indices (0 sqrtX, 1 sqrtY, 2 sqrtW) of every layer:
+ * gates_host[layer * n_qubits + q]; capacity n_layers_1q * n_qubits. */
+rcs_status rcs_circuit_one_qubit_gates(rcs_circuit c, int32_t* gates_host);
+
+/* The compiled MPS schedule.  snake_host[pos] = qubit at MPS position pos
+ * (boustrophedon order, rows along the short side).  ops_host[4*o + 0..3] =
+ * {kind, arg, gate, cycle}: kind 0 = single-qubit layer (arg = layer index),
+ * kind 1 = two-site update at positions (arg, arg+1) with gate 0 = fSim,
+ * 1 = SWAP.  Vertical couplers become SWAP chains around the fSim update.
+ * Capacities: n_qubits and 4 * n_ops. */
+rcs_status rcs_circuit_schedule(rcs_circuit c, int32_t* snake_host, int32_t* ops_host);
+
+/* ------------------------------------------------------------------- build */
+typedef enum { RCS_PREC_C128 = 0, RCS_PREC_C64 = 1, RCS_PREC_SPLIT_BF16 = 2 } rcs_precision;
+typedef enum {
+  RCS_RANK_FULL_SVD = 0,  /* fp64 one-sided Jacobi SVD + threshold rank rule   */
+  RCS_RANK_LEARNED = 1,   /* network-predicted rank, fp32 randomized SVD, judge */
+  RCS_RANK_RSVD_AT_CAP = 2 /* fp32 randomized SVD at rank min(chi, m), judge    */
+} rcs_rank_mode;
+
+typedef struct {
+  int32_t contraction;     /* rcs_precision of the two-site contraction      */
+  int32_t rank_mode;       /* rcs_rank_mode                                   */
+  double fallback_tau;     /* judge slack; < 0 forces the fp64 fall-back      */
+  const float* mlp_weights_host; /* packed fp32 weights (learned mode)        */
+  int64_t mlp_count;       /* number of floats in mlp_weights_host            */
+  int32_t rsvd_oversample; /* p (default 16)                                  */
+  int32_t rsvd_power_iters;/* q (default 2)                                   */
+  uint64_t rsvd_seed;      /* sketch seed                                     */
+  void* stream;            /* hipStream_t for all work; NULL = null stream    */
+  int32_t log_spectra;     /* 1: keep every update's singular spectrum        */
+  int32_t max_ops;         /* < 0: whole schedule; else stop after max_ops    */
+  int32_t canonicalize;    /* 1 (default): end right-canonical, unit norm     */
+} rcs_build_opts;
+
+/* Fills *opts with defaults: C128, FULL_SVD, tau 1e-6, p 16, q 2, null
+ * stream, no logging, whole schedule, canonicalize. */
+void rcs_build_opts_default(rcs_build_opts* opts);
+
+/* Builds the MPS output state of the circuit with bond cap chi >= 1 and
+ * per-step relative discarded-weight threshold 0 <= trunc_eps < 1, in fp64
+ * with the full SVD (rcs_build_state_ex with default options).  The state
+ * owns its device memory and does not borrow the circuit.  Errors:
+ * INVALID_ARG, OUT_OF_MEMORY, DEVICE, NUMERIC (SVD not converged / NaN). */
+rcs_status rcs_build_state(rcs_circuit circuit, int32_t chi, double trunc_eps, rcs_state* out);
+rcs_status rcs_build_state_ex(rcs_circuit circuit, int32_t chi, double trunc_eps,
+                              const rcs_build_opts* opts, rcs_state* out);
+
+/* Builds n states, one per circuit, sharing one set of workspaces, each with
+ * its own chi[i] and eps[i].  out[0..n-1] receive handles (all or none). */
+rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, const double* eps,
+                           int32_t n, const rcs_build_opts* opts, rcs_state* out);
+
+/* ---------------------------------------------------------------- sampling
+ * Section 3.2 stage 3: n_shots measurement shots from a right-canonical,
+ * unit-norm state.  Shot i, site k (MPS order): w_s = v A_k^s, p_s = |w_s|^2
+ * in fp64, u = uniform from Philox(seed; shot i, site k), bit = (u*(p0+p1)
+ * >= p0), v <- w_bit.  bits_dev[i] receives the bitstring of shot
+ * first_shot + i, log2p_dev[i] (nullable) log2 |psi(b)|^2.  Shots depend
+ * only on (state, seed, shot index), so ranges computed separately and
+ * concatenated equal one call.  Errors: INVALID_ARG (null bits_dev), STATE
+ * (state not canonical). */
+rcs_status rcs_sample(rcs_state s, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
+                      double* log2p_dev);
+rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                            uint64_t* bits_dev, double* log2p_dev);
+
+/* Shots from n states in one launch sequence: shot j of state i goes to
+ * bits_dev[i * n_shots + j] (and log2p_dev likewise, nullable). */
+rcs_status rcs_sample_batch(const rcs_state* states, int32_t n, uint64_t n_shots, uint64_t seed,
+                            uint64_t* bits_dev, double* log2p_dev);
+
+/* psi(b) for m bitstrings: amps_dev[2i], amps_dev[2i+1] = re, im. */
+rcs_status rcs_amplitudes(rcs_state s, const uint64_t* bits_dev, uint64_t m, double* amps_dev);
+
+/* Section 5.1 linear XEB: F = 2^n mean_i p_ref_i - 1 and its standard error
+ * std(2^n p_ref) / sqrt(m) (m - 1 denominator), from m >= 2 reference
+ * probabilities on the device; fixed-order fp64 reduction.  Host outputs. */
+rcs_status rcs_xeb(int32_t n_qubits, const double* p_ref_dev, uint64_t m, double* xeb_host,
+                   double* stderr_host);
+/* The same from log2 probabilities (as written by rcs_sample). */
+rcs_status rcs_xeb_log2(int32_t n_qubits, const double* log2p_dev, uint64_t m, double* xeb_host,
+                        double* stderr_host);
+/* Scores m bitstrings with ref's |psi|^2. */
+rcs_status rcs_xeb_state(rcs_state ref, const uint64_t* bits_dev, uint64_t m, double* xeb_host,
+                         double* stderr_host);
+
+/* ------------------------------------------------------------ state access */
+typedef struct {
+  int32_t n_qubits;
+  int32_t max_bond;
+  int32_t center;          /* orthogonality centre position               */
+  int32_t canonical;       /* 1 when right-canonical with unit norm       */
+  int32_t n_truncations;   /* two-site updates performed                  */
+  int32_t n_fallbacks;     /* learned/rsvd steps redone with the full SVD  */
+  int32_t n_rsvd_accepted;
+  int32_t jacobi_sweeps_max;
+  double log_fidelity_est; /* sum log(1 - eps_step)                       */
+  double sum_eps;
+  double build_seconds;    /* device time from first kernel to last       */
+  double svd_seconds;      /* part spent in SVD/RSVD kernels (if timed)   */
+  int64_t device_bytes;    /* MPS + workspace bytes held                  */
+} rcs_state_info;
+
+rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out);
+/* bond_dims_host[k] = dimension between positions k and k+1 (n-1 values);
+ * snake_host[pos] = qubit at position pos (n values).  Either may be NULL. */
+rcs_status rcs_state_layout(rcs_state s, int32_t* bond_dims_host, int32_t* snake_host);
+rcs_status rcs_state_set_stream(rcs_state s, void* stream);
+
+/* Copies the site tensors to the host: tensors_host receives, for positions
+ * 0..n-1 in order, A_k with shape (dim_k, 2, dim_{k+1}) in row-major complex
+ * (2 doubles per entry); count_doubles is the capacity in doubles (query
+ * the needed size with tensors_host = NULL: *needed_doubles is set). */
+rcs_status rcs_state_export(rcs_state s, double* tensors_host, int64_t count_doubles,
+                            int64_t* needed_doubles);
+/* Creates a state from host site tensors in the export layout.  dims_host
+ * has n+1 entries (dims[0] = dims[n] = 1), snake_host n entries (a
+ * permutation of 0..n-1).  canonical = 1 asserts the tensors are
+ * right-canonical with unit norm (required by rcs_sample).  Errors:
+ * INVALID_ARG for bad dims or permutation. */
+rcs_status rcs_state_import(int32_t n, const int32_t* dims_host, const int32_t* snake_host,
+                            const double* tensors_host, int32_t canonical, void* stream,
+                            rcs_state* out);
+void rcs_state_destroy(rcs_state s);
+
+/* Per-update record of a build with log_spectra = 1: count, then for record
+ * r: meta_host[6r..6r+5] = {position, cycle, m (singular values), kept rank,
+ * chi_l, chi_r} and the m singular values (descending) appended to
+ * values_host in record order.  Query sizes with NULL outputs. */
+rcs_status rcs_state_spectra(rcs_state s, int32_t* n_records, int64_t* n_values,
+                             int32_t* meta_host, double* values_host);
+
+/* -------------------------------------------------------- kernel-level calls
+ * Exposed for parity tests of individual stages and for the training driver.
+ * All device pointers, all ordered on `stream`. */
+
+/* Thin SVD of a complex len x cnt matrix given column-major in x_dev
+ * (column j at x_dev + 2*len*j) by one-sided block Jacobi in fp64:
+ * s_dev[cnt] = singular values in descending order, u_dev (len x cnt,
+ * column-major) = left singular vectors (zero columns where s = 0).
+ * x_dev is overwritten.  Errors: NUMERIC if not converged. */
+rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev, double* u_dev,
+                          void* stream);
+
+/* Two-site contraction: theta'[(s1,a),(s2,c)] = sum_{s1',s2'} G[(s1,s2),(s1',s2')]
+ * sum_b A[a,s1',b] B[b,s2',c] with A (dl,2,dm), B (dm,2,dr) in export
+ * layout, G 4x4 row-major complex; out_dev receives the (2dl) x (2dr)
+ * matrix column-major.  precision = rcs_precision. */
+rcs_status rcs_two_site(int32_t dl, int32_t dm, int32_t dr, const double* a_dev,
+                        const double* b_dev, const double* gate_host, int32_t precision,
+                        double* out_dev, void* stream);
+
+/* Randomized SVD (fp32): len x cnt column-major complex fp64 input, sketch
+ * width l, q power iterations, sketch entries {1,i,-1,-i} from Philox(seed;
+ * (row, col, step, 4)).  s_dev[l] receives singular values (descending).
+ * fro2_host receives ||M||_F^2 (fp64). */
+rcs_status rcs_rsvd(int32_t len, int32_t cnt, const double* x_dev, int32_t l, int32_t q,
+                    uint64_t seed, uint64_t step, double* s_dev, double* fro2_host, void* stream);
+
+/* Spectrum features: 64-bin histogram of log10(s^2/sum s^2) (0.25 decade
+ * bins over [-16,0), clamped) of s_dev[0..k-1], normalised to sum 1, then
+ * bond/(n-2), cycle/n_cycles: 66 floats to feat_dev. */
+rcs_status rcs_spectrum_features(const double* s_dev, int32_t k, int32_t bond, int32_t n_sites,
+                                 int32_t cycle, int32_t n_cycles, float* feat_dev, void* stream);
+
+/* Rank network 66-128-128-32 (ReLU), fp32, packed weights W1,b1,W2,b2,W3,b3
+ * (row-major W[out][in]).  Forward: out_dev[batch*32]. */
+#define RCS_MLP_PARAMS (66 * 128 + 128 + 128 * 128 + 128 + 128 * 32 + 32)
+rcs_status rcs_mlp_forward(const float* w_dev, const float* x_dev, int32_t batch, float* out_dev,
+                           void* stream);
+/* Mean-squared-error loss and its gradient for every parameter. */
+rcs_status rcs_mlp_backward(const float* w_dev, const float* x_dev, const float* y_dev,
+                            int32_t batch, float* grad_dev, float* loss_dev, void* stream);
+/* Adam step (bias-corrected, step >= 1) on count parameters in place. */
+rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                        int32_t count, int32_t step, float lr, float beta1, float beta2,
+                        float eps, void* stream);
+
+/* ---------------------------------------------------------------- misc */
+const char* rcs_last_error(void);
+/* Library version string. */
+const char* rcs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCS_H */

@@ -1,0 +1,301 @@
+// C ABI entry points: circuits, state access, sampling, amplitudes, XEB.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "circuit.h"
+#include "state.h"
+
+namespace rcs {
+static thread_local std::string g_last_error;
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+}  // namespace rcs
+
+#define RCS_API_BEGIN try {
+#define RCS_API_END                                      \
+  }                                                      \
+  catch (const rcs::Error& e) {                          \
+    rcs::set_last_error(e.what());                       \
+    return e.status;                                     \
+  }                                                      \
+  catch (const std::bad_alloc&) {                        \
+    rcs::set_last_error("host allocation failed");       \
+    return RCS_ERR_OUT_OF_MEMORY;                        \
+  }                                                      \
+  catch (const std::exception& e) {                      \
+    rcs::set_last_error(e.what());                       \
+    return RCS_ERR_DEVICE;                               \
+  }                                                      \
+  return RCS_OK;
+
+extern "C" {
+
+const char* rcs_last_error(void) { return rcs::g_last_error.c_str(); }
+const char* rcs_version(void) { return "librcs 0.1 gfx950"; }
+
+// ---------------------------------------------------------------- circuits
+rcs_status rcs_circuit_create(const rcs_circuit_desc* desc, rcs_circuit* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(desc && out, "null argument");
+  *out = nullptr;
+  auto c = std::make_unique<rcs_circuit_s>();
+  rcs::generate_circuit(*desc, *c);
+  *out = c.release();
+  RCS_API_END
+}
+
+void rcs_circuit_destroy(rcs_circuit c) { delete c; }
+
+rcs_status rcs_circuit_info(rcs_circuit c, int32_t* n_qubits, int32_t* n_layers_1q,
+                            int32_t* n_ops, int32_t* n_updates) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(c, "null circuit");
+  if (n_qubits) *n_qubits = c->n;
+  if (n_layers_1q) *n_layers_1q = (int32_t)c->layers_1q.size();
+  if (n_ops) *n_ops = (int32_t)c->ops.size();
+  if (n_updates) *n_updates = c->n_updates;
+  RCS_API_END
+}
+
+rcs_status rcs_circuit_one_qubit_gates(rcs_circuit c, int32_t* gates_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(c && gates_host, "null argument");
+  for (size_t l = 0; l < c->layers_1q.size(); ++l)
+    for (int q = 0; q < c->n; ++q) gates_host[l * c->n + q] = c->layers_1q[l][q];
+  RCS_API_END
+}
+
+rcs_status rcs_circuit_schedule(rcs_circuit c, int32_t* snake_host, int32_t* ops_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(c, "null circuit");
+  if (snake_host)
+    for (int p = 0; p < c->n; ++p) snake_host[p] = c->snake[p];
+  if (ops_host)
+    for (size_t o = 0; o < c->ops.size(); ++o) {
+      ops_host[4 * o + 0] = c->ops[o].kind;
+      ops_host[4 * o + 1] = c->ops[o].arg;
+      ops_host[4 * o + 2] = c->ops[o].gate;
+      ops_host[4 * o + 3] = c->ops[o].cycle;
+    }
+  RCS_API_END
+}
+
+// ------------------------------------------------------------ state access
+rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s && out, "null argument");
+  rcs_state_info inf{};
+  inf.n_qubits = s->n;
+  inf.max_bond = *std::max_element(s->dims.begin(), s->dims.end());
+  inf.center = s->center;
+  inf.canonical = s->canonical ? 1 : 0;
+  inf.n_truncations = s->n_trunc;
+  inf.n_fallbacks = s->n_fallback;
+  inf.n_rsvd_accepted = s->n_rsvd_ok;
+  inf.jacobi_sweeps_max = s->jacobi_sweeps_max;
+  inf.log_fidelity_est = s->log_fest;
+  inf.sum_eps = s->sum_eps;
+  inf.build_seconds = s->build_seconds;
+  inf.svd_seconds = s->svd_seconds;
+  inf.device_bytes = (int64_t)(s->slab.bytes + s->spare.bytes);
+  *out = inf;
+  RCS_API_END
+}
+
+rcs_status rcs_state_layout(rcs_state s, int32_t* bond_dims_host, int32_t* snake_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  if (bond_dims_host)
+    for (int k = 0; k < s->n - 1; ++k) bond_dims_host[k] = s->dims[k + 1];
+  if (snake_host)
+    for (int k = 0; k < s->n; ++k) snake_host[k] = s->pi[k];
+  RCS_API_END
+}
+
+rcs_status rcs_state_set_stream(rcs_state s, void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  s->stream = rcs::as_stream(stream);
+  RCS_API_END
+}
+
+rcs_status rcs_state_export(rcs_state s, double* tensors_host, int64_t count_doubles,
+                            int64_t* needed_doubles) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  int64_t need = 0;
+  for (int k = 0; k < s->n; ++k) need += (int64_t)s->dims[k] * 2 * s->dims[k + 1] * 2;
+  if (needed_doubles) *needed_doubles = need;
+  if (!tensors_host) return RCS_OK;
+  RCS_REQUIRE(count_doubles >= need, "output buffer too small");
+  std::vector<double2> tmp;
+  int64_t off = 0;
+  for (int k = 0; k < s->n; ++k) {
+    const int dl = s->dims[k], dr = s->dims[k + 1];
+    tmp.resize((size_t)dl * 2 * dr);
+    HIP_OK(hipMemcpyAsync(tmp.data(), s->site[k], tmp.size() * sizeof(double2),
+                          hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    // device [s][a][b] -> host (a, s, b)
+    for (int a = 0; a < dl; ++a)
+      for (int ph = 0; ph < 2; ++ph)
+        for (int b = 0; b < dr; ++b) {
+          const double2 v = tmp[((size_t)ph * dl + a) * dr + b];
+          const int64_t o = off + (((int64_t)a * 2 + ph) * dr + b) * 2;
+          tensors_host[o] = v.x;
+          tensors_host[o + 1] = v.y;
+        }
+    off += (int64_t)dl * 2 * dr * 2;
+  }
+  RCS_API_END
+}
+
+rcs_status rcs_state_import(int32_t n, const int32_t* dims_host, const int32_t* snake_host,
+                            const double* tensors_host, int32_t canonical, void* stream,
+                            rcs_state* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(out && dims_host && snake_host && tensors_host, "null argument");
+  *out = nullptr;
+  RCS_REQUIRE(n >= 1 && n <= 64, "n must be in [1, 64]");
+  RCS_REQUIRE(dims_host[0] == 1 && dims_host[n] == 1, "boundary bond dimensions must be 1");
+  std::vector<char> seen(n, 0);
+  for (int k = 0; k < n; ++k) {
+    RCS_REQUIRE(snake_host[k] >= 0 && snake_host[k] < n && !seen[snake_host[k]],
+                "snake must be a permutation of 0..n-1");
+    seen[snake_host[k]] = 1;
+  }
+  int chi = 1;
+  for (int k = 0; k <= n; ++k) {
+    RCS_REQUIRE(dims_host[k] >= 1 && dims_host[k] <= 8192, "bond dimension out of range");
+    chi = std::max(chi, (int)dims_host[k]);
+  }
+  auto st = std::make_unique<rcs_state_s>();
+  st->stream = rcs::as_stream(stream);
+  HIP_OK(hipGetDevice(&st->device));
+  rcs::state_alloc(*st, n, chi);
+  for (int k = 0; k <= n; ++k)
+    RCS_REQUIRE(dims_host[k] <= st->cap[k], "bond dimension exceeds 2^min(k, n-k)");
+  st->dims.assign(dims_host, dims_host + n + 1);
+  st->pi.assign(snake_host, snake_host + n);
+  std::vector<double2> tmp;
+  int64_t off = 0;
+  for (int k = 0; k < n; ++k) {
+    const int dl = st->dims[k], dr = st->dims[k + 1];
+    tmp.resize((size_t)dl * 2 * dr);
+    for (int a = 0; a < dl; ++a)
+      for (int ph = 0; ph < 2; ++ph)
+        for (int b = 0; b < dr; ++b) {
+          const int64_t o = off + (((int64_t)a * 2 + ph) * dr + b) * 2;
+          tmp[((size_t)ph * dl + a) * dr + b] = make_double2(tensors_host[o], tensors_host[o + 1]);
+        }
+    HIP_OK(hipMemcpyAsync(st->site[k], tmp.data(), tmp.size() * sizeof(double2),
+                          hipMemcpyHostToDevice, st->stream));
+    HIP_OK(hipStreamSynchronize(st->stream));
+    off += (int64_t)dl * 2 * dr * 2;
+  }
+  st->canonical = canonical != 0;
+  st->center = 0;
+  *out = st.release();
+  RCS_API_END
+}
+
+void rcs_state_destroy(rcs_state s) {
+  if (s && s->stream) (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
+
+rcs_status rcs_state_spectra(rcs_state s, int32_t* n_records, int64_t* n_values,
+                             int32_t* meta_host, double* values_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  int64_t nv = 0;
+  for (auto& r : s->spectra) nv += (int64_t)r.values.size();
+  if (n_records) *n_records = (int32_t)s->spectra.size();
+  if (n_values) *n_values = nv;
+  int64_t o = 0;
+  for (size_t i = 0; i < s->spectra.size(); ++i) {
+    const auto& r = s->spectra[i];
+    if (meta_host) {
+      int32_t* m = meta_host + 6 * i;
+      m[0] = r.pos;
+      m[1] = r.cycle;
+      m[2] = r.m;
+      m[3] = r.kept;
+      m[4] = r.chi_l;
+      m[5] = r.chi_r;
+    }
+    if (values_host) std::copy(r.values.begin(), r.values.end(), values_host + o);
+    o += (int64_t)r.values.size();
+  }
+  RCS_API_END
+}
+
+// ------------------------------------------------------------- sampling
+rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                            uint64_t* bits_dev, double* log2p_dev) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  RCS_REQUIRE(bits_dev || n_shots == 0, "null bits_dev");
+  if (!s->canonical) rcs::fail(RCS_ERR_STATE, "rcs_sample: state is not right-canonical");
+  rcs::run_chain(*s, first_shot, n_shots, seed, 0, bits_dev, log2p_dev, nullptr, nullptr);
+  RCS_API_END
+}
+
+rcs_status rcs_sample(rcs_state s, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
+                      double* log2p_dev) {
+  return rcs_sample_range(s, 0, n_shots, seed, bits_dev, log2p_dev);
+}
+
+rcs_status rcs_sample_batch(const rcs_state* states, int32_t n, uint64_t n_shots, uint64_t seed,
+                            uint64_t* bits_dev, double* log2p_dev) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(states && n >= 0, "bad arguments");
+  RCS_REQUIRE(bits_dev || n_shots == 0, "null bits_dev");
+  for (int i = 0; i < n; ++i) {
+    RCS_REQUIRE(states[i], "null state in batch");
+    if (!states[i]->canonical) rcs::fail(RCS_ERR_STATE, "state in batch is not right-canonical");
+  }
+  for (int i = 0; i < n; ++i)
+    rcs::run_chain(*states[i], 0, n_shots, seed, 0, bits_dev + (uint64_t)i * n_shots,
+                   log2p_dev ? log2p_dev + (uint64_t)i * n_shots : nullptr, nullptr, nullptr);
+  RCS_API_END
+}
+
+rcs_status rcs_amplitudes(rcs_state s, const uint64_t* bits_dev, uint64_t m, double* amps_dev) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  RCS_REQUIRE((bits_dev && amps_dev) || m == 0, "null device pointer");
+  rcs::run_chain(*s, 0, m, 0, 1, nullptr, nullptr, bits_dev, amps_dev);
+  RCS_API_END
+}
+
+rcs_status rcs_xeb(int32_t n_qubits, const double* p_ref_dev, uint64_t m, double* xeb_host,
+                   double* stderr_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(p_ref_dev && xeb_host && stderr_host, "null argument");
+  rcs::xeb_reduce(n_qubits, p_ref_dev, m, false, xeb_host, stderr_host, nullptr);
+  RCS_API_END
+}
+
+rcs_status rcs_xeb_log2(int32_t n_qubits, const double* log2p_dev, uint64_t m, double* xeb_host,
+                        double* stderr_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(log2p_dev && xeb_host && stderr_host, "null argument");
+  rcs::xeb_reduce(n_qubits, log2p_dev, m, true, xeb_host, stderr_host, nullptr);
+  RCS_API_END
+}
+
+}  // extern "C"
+
+extern "C" rcs_status rcs_xeb_state(rcs_state ref, const uint64_t* bits_dev, uint64_t m,
+                                    double* xeb_host, double* stderr_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(ref && bits_dev && xeb_host && stderr_host, "null argument");
+  rcs::DevBuf amps, p;
+  amps.ensure((size_t)m * sizeof(double2));
+  p.ensure((size_t)m * sizeof(double));
+  rcs::run_chain(*ref, 0, m, 0, 1, nullptr, nullptr, bits_dev, amps.as<double>());
+  rcs::abs2_to(amps.as<double2>(), m, p.as<double>(), ref->stream);
+  rcs::xeb_reduce(ref->n, p.as<double>(), m, false, xeb_host, stderr_host, ref->stream);
+  RCS_API_END
+}

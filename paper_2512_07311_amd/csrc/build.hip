@@ -1,0 +1,818 @@
+// State construction (Section 3.2, stage 1) as a snake-ordered MPS.
+//
+// Schedule ops run in order on the state's stream:
+//   single-qubit layer : A_p^s <- sum_t U[s,t] A_p^t on every site (one launch)
+//   two-site update    : centre moves (exact SVD orthogonalisations) until the
+//                        centre is in {i, i+1}; T^{s1' s2'} = A_i^{s1'} A_{i+1}^{s2'}
+//                        on the matrix cores; theta' = G T mixed with the 4x4
+//                        gate (fSim or SWAP of the swap network) while laying out
+//                        the Jacobi input; one-sided Jacobi SVD in fp64;
+//                        descending sort, rank rule, renormalisation; U_k and
+//                        S_k V_k^H written back as the two site tensors.
+//   end                : centre moved to position 0, A_0 normalised, so the
+//                        state is right-canonical with unit norm.
+// The Jacobi SVD orthogonalises whichever side of the two-site matrix has
+// fewer columns; for square matrices it picks the side that leaves the
+// orthogonality centre where the next update needs it.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+
+#include "build.h"
+#include "circuit.h"
+#include "gemm_f64.h"
+#include "jacobi.h"
+#include "state.h"
+
+namespace rcs {
+
+// ------------------------------------------------------------- allocation
+size_t site_capacity(const rcs_state_s& st, int) {
+  int mx = 1;
+  for (int c : st.cap) mx = std::max(mx, c);
+  return (size_t)mx * 2 * mx;
+}
+
+void state_alloc(rcs_state_s& st, int n, int chi) {
+  st.n = n;
+  st.chi = chi;
+  st.cap.assign(n + 1, 1);
+  for (int b = 0; b <= n; ++b) {
+    int e = std::min(b, n - b);
+    int64_t c = (e >= 30) ? (int64_t)1 << 30 : (int64_t)1 << e;
+    st.cap[b] = (int)std::min<int64_t>(c, chi);
+  }
+  st.dims.assign(n + 1, 1);
+  st.pi.resize(n);
+  for (int k = 0; k < n; ++k) st.pi[k] = k;
+  const size_t per = site_capacity(st, 0);
+  st.slab.ensure((size_t)n * per * sizeof(double2));
+  st.spare.ensure(per * sizeof(double2));
+  st.site.resize(n);
+  for (int k = 0; k < n; ++k) st.site[k] = st.slab.as<double2>() + (size_t)k * per;
+  st.spare_ptr = st.spare.as<double2>();
+  HIP_OK(hipMemsetAsync(st.slab.p, 0, st.slab.bytes, st.stream));
+  // |0>: A_k[s=0][0][0] = 1
+  const double2 one = make_double2(1.0, 0.0);
+  for (int k = 0; k < n; ++k)
+    HIP_OK(hipMemcpyAsync(st.site[k], &one, sizeof(double2), hipMemcpyHostToDevice, st.stream));
+  HIP_OK(hipStreamSynchronize(st.stream));
+  st.center = 0;
+  st.canonical = true;
+}
+
+// ---------------------------------------------------------------- kernels
+struct Layer1q {
+  double2* site[64];
+  int dl[64], dr[64];
+  uint8_t gate[64];
+};
+__constant__ double2 c_gates1q[3][4];
+
+__global__ void k_apply_1q(Layer1q L) {
+  const int k = blockIdx.y;
+  const int64_t cnt = (int64_t)L.dl[k] * L.dr[k];
+  double2* a = L.site[k];
+  const double2* U = c_gates1q[L.gate[k]];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double2 x0 = a[e], x1 = a[cnt + e];
+    double2 y0 = make_double2(U[0].x * x0.x - U[0].y * x0.y + U[1].x * x1.x - U[1].y * x1.y,
+                              U[0].x * x0.y + U[0].y * x0.x + U[1].x * x1.y + U[1].y * x1.x);
+    double2 y1 = make_double2(U[2].x * x0.x - U[2].y * x0.y + U[3].x * x1.x - U[3].y * x1.y,
+                              U[2].x * x0.y + U[2].y * x0.x + U[3].x * x1.y + U[3].y * x1.x);
+    a[e] = y0;
+    a[cnt + e] = y1;
+  }
+}
+
+// T[q][a][c] = A_i^{s1'}[a][:] . A_{i+1}^{s2'}[:][c], q = 2 s1' + s2'
+__global__ __launch_bounds__(GT_THREADS) void k_two_site_f64(const double2* A, const double2* B,
+                                                            double2* T, int dl, int dm, int dr) {
+  __shared__ SmemC64 sm;
+  const int q = blockIdx.z, s1 = q >> 1, s2 = q & 1;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  const double2* a = A + (int64_t)s1 * dl * dm;
+  const double2* b = B + (int64_t)s2 * dm * dr;
+  auto fa = [&](int m, int k) -> double2 { return a[(int64_t)m * dm + k]; };
+  auto fb = [&](int k, int n) -> double2 { return b[(int64_t)k * dr + n]; };
+  LoadA<decltype(fa), true> la{fa, m0, dl, dm};
+  LoadB<decltype(fb), true> lb{fb, n0, dm, dr};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, dm, sm, acc);
+  double2* t = T + (int64_t)q * dl * dr;
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    int m = m0 + r, n = n0 + c;
+    if (m < dl && n < dr) t[(int64_t)m * dr + n] = make_double2(re, im);
+  });
+}
+
+struct Gate4 {
+  double2 g[16];
+};
+
+// theta'[s1][s2][a][c] = sum_q G[(s1 s2), q] T[q][a][c] written to X (and X0)
+// column-major.  case 1: X = M (rows (s1,a), cols (s2,c)); case 2: X = M^H.
+__global__ void k_mix_gate(const double2* T, Gate4 G, int dl, int dr, int orient, double2* X,
+                           double2* X0, int ldx) {
+  const int64_t tot = (int64_t)dl * dr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int a, c;
+    if (orient == 1) {  // a fastest: column-major writes along rows (s1, a)
+      a = (int)(e % dl);
+      c = (int)(e / dl);
+    } else {            // c fastest: rows are (s2, c)
+      c = (int)(e % dr);
+      a = (int)(e / dr);
+    }
+    double2 t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = T[(int64_t)q * tot + (int64_t)a * dr + c];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double2 g = G.g[o * 4 + q];
+        re += g.x * t[q].x - g.y * t[q].y;
+        im += g.x * t[q].y + g.y * t[q].x;
+      }
+      const int s1 = o >> 1, s2 = o & 1;
+      int64_t idx;
+      double2 v;
+      if (orient == 1) {
+        idx = (int64_t)(s2 * dr + c) * ldx + (s1 * dl + a);
+        v = make_double2(re, im);
+      } else {
+        idx = (int64_t)(s1 * dl + a) * ldx + (s2 * dr + c);
+        v = make_double2(re, -im);
+      }
+      X[idx] = v;
+      X0[idx] = v;
+    }
+  }
+}
+
+// Single-site orthogonalisation input.  right: X[b][(s,a)] = A[s][a][b];
+// left: X[a][(s,b)] = conj(A[s][a][b]).
+__global__ void k_load_site(const double2* A, int dl, int dr, int right, double2* X, double2* X0,
+                            int ldx) {
+  const int64_t tot = (int64_t)2 * dl * dr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    // e enumerates the device layout [s][a][b]
+    const int b = (int)(e % dr);
+    const int a = (int)((e / dr) % dl);
+    const int s = (int)(e / ((int64_t)dl * dr));
+    double2 v = A[e];
+    int64_t idx;
+    if (right) {
+      idx = (int64_t)b * ldx + s * dl + a;
+    } else {
+      idx = (int64_t)a * ldx + s * dr + b;
+      v.y = -v.y;
+    }
+    X[idx] = v;
+    X0[idx] = v;
+  }
+}
+
+__global__ void k_colnorm(const double2* X, int ldx, int len, double* sigma) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const double2* col = X + (int64_t)j * ldx;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < len; r += 256) s += col[r].x * col[r].x + col[r].y * col[r].y;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[j] = sqrt(red[0]);
+}
+
+// Sort sigma descending (ties by index), apply the rank rule.
+//  w = sum s^2; s^2 <= 1e-24 w counts as zero; tail(k) = sum_{r>=k} s_r^2
+//  from the smallest upward; k_eps = min{k>=1 : tail(k) <= eps w};
+//  k = min(k_eps, cap); eps_step = tail(k)/w; nrm = sqrt(sum_{r<k} s_r^2).
+struct RankOut {
+  int k;
+  int nnz;
+  double eps_step, w, nrm;
+  int bad;
+};
+
+constexpr int SORT_MAX = 4096;
+
+__global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt, int cap,
+                                                   double eps, double* sorted, int* order,
+                                                   RankOut* out) {
+  __shared__ double key[SORT_MAX];
+  __shared__ int idx[SORT_MAX];
+  int npow = 1;
+  while (npow < cnt) npow <<= 1;
+  for (int i = threadIdx.x; i < npow; i += blockDim.x) {
+    key[i] = i < cnt ? sigma[i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  // bitonic sort: descending by key, ascending by index for equal keys
+  for (int size = 2; size <= npow; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < npow; i += blockDim.x) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool desc = ((i & size) == 0);
+          double ki = key[i], kj = key[j];
+          int ii = idx[i], ij = idx[j];
+          bool i_first = (ki > kj) || (ki == kj && ii < ij);
+          bool swap = desc ? !i_first : i_first;
+          if (swap) {
+            key[i] = kj;
+            key[j] = ki;
+            idx[i] = ij;
+            idx[j] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    sorted[i] = key[i];
+    order[i] = idx[i];
+  }
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    int bad = 0;
+    for (int i = cnt - 1; i >= 0; --i) {
+      double v = key[i];
+      if (!(v == v) || v > 1e300) bad = 1;
+      w += v * v;
+    }
+    const double floor = 1e-24 * w;
+    int nnz = 0;
+    for (int i = 0; i < cnt; ++i)
+      if (key[i] * key[i] > floor) nnz = i + 1;
+    // tail sums from the smallest upward; find the smallest k >= 1 with
+    // tail(k) <= eps w by scanning k downward while the condition holds.
+    double tail = 0.0;
+    int k_eps = cnt;
+    double tail_at[1];
+    (void)tail_at;
+    // tail(cnt) = 0 always qualifies; walk down accumulating.
+    double tail_k = 0.0;
+    for (int k = cnt; k >= 1; --k) {
+      // tail currently = tail(k)
+      if (tail <= eps * w) {
+        k_eps = k;
+        tail_k = tail;
+      } else {
+        break;
+      }
+      double v = key[k - 1];
+      double v2 = v * v;
+      tail += (v2 <= floor) ? 0.0 : v2;
+    }
+    int k = min(k_eps, cap);
+    double tk = 0.0;
+    if (k == k_eps) {
+      tk = tail_k;
+    } else {
+      for (int i = cnt - 1; i >= k; --i) {
+        double v2 = key[i] * key[i];
+        tk += (v2 <= floor) ? 0.0 : v2;
+      }
+    }
+    double kept = 0.0;
+    for (int i = 0; i < k; ++i) kept += key[i] * key[i];
+    out->k = k;
+    out->nnz = nnz;
+    out->eps_step = (w > 0.0) ? tk / w : 0.0;
+    out->w = w;
+    out->nrm = sqrt(kept);
+    out->bad = bad || !(w > 0.0);
+  }
+}
+
+// Wn[:, j] = X[:, order[j]] / sorted[j], j < k  (all ldx rows)
+__global__ void k_gather_normalize(const double2* X, int ldx, const int* order, const double* sorted,
+                                   double2* Wn) {
+  const int j = blockIdx.y;
+  const double inv = 1.0 / sorted[j];
+  const double2* src = X + (int64_t)order[j] * ldx;
+  double2* dst = Wn + (int64_t)j * ldx;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ldx; r += gridDim.x * blockDim.x) {
+    double2 v = src[r];
+    dst[r] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
+// P (k x cnt, row-major) = scale * Wn^H X0
+__global__ __launch_bounds__(GT_THREADS) void k_project(const double2* Wn, const double2* X0, int ldx,
+                                                       int len, int k, int cnt, double scale,
+                                                       double2* P) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int kk) -> double2 {
+    double2 v = Wn[(int64_t)m * ldx + kk];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int kk, int n) -> double2 { return X0[(int64_t)n * ldx + kk]; };
+  LoadA<decltype(fa), true> la{fa, m0, k, len};
+  LoadB<decltype(fb), false> lb{fb, n0, len, cnt};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, len, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    int m = m0 + r, n = n0 + c;
+    if (m < k && n < cnt) P[(int64_t)m * cnt + n] = make_double2(re * scale, im * scale);
+  });
+}
+
+// Write the two factors of a split back into site layout.
+//  case 1 (X = M):   A_i[s1][a][j] = Wn[j][(s1,a)],  A_{i+1}[s2][j][c] = P[j][(s2,c)]
+//  case 2 (X = M^H): A_{i+1}[s2][j][c] = conj Wn[j][(s2,c)], A_i[s1][a][j] = conj P[j][(s1,a)]
+__global__ void k_write_split(const double2* Wn, int ldx, const double2* P, int cnt, int k, int dl,
+                              int dr, int orient, double2* Ai, double2* Aj) {
+  const int64_t n1 = (int64_t)2 * dl * k, n2 = (int64_t)2 * k * dr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n1 + n2;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < n1) {  // A_i element [s1][a][j]
+      const int j = (int)(e % k);
+      const int a = (int)((e / k) % dl);
+      const int s1 = (int)(e / ((int64_t)k * dl));
+      double2 v;
+      if (orient == 1) {
+        v = Wn[(int64_t)j * ldx + s1 * dl + a];
+      } else {
+        v = P[(int64_t)j * cnt + s1 * dl + a];
+        v.y = -v.y;
+      }
+      Ai[e] = v;
+    } else {       // A_{i+1} element [s2][j][c]
+      const int64_t f = e - n1;
+      const int c = (int)(f % dr);
+      const int j = (int)((f / dr) % k);
+      const int s2 = (int)(f / ((int64_t)dr * k));
+      double2 v;
+      if (orient == 1) {
+        v = P[(int64_t)j * cnt + s2 * dr + c];
+      } else {
+        v = Wn[(int64_t)j * ldx + s2 * dr + c];
+        v.y = -v.y;
+      }
+      Aj[f] = v;
+    }
+  }
+}
+
+// Orthonormal factor of a single-site split.  right: A[s][a][j] = Wn[j][(s,a)];
+// left: A[s][j][b] = conj Wn[j][(s,b)].
+__global__ void k_write_ortho(const double2* Wn, int ldx, int k, int dl, int dr, int right,
+                              double2* A) {
+  const int64_t tot = right ? (int64_t)2 * dl * k : (int64_t)2 * k * dr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double2 v;
+    if (right) {
+      const int j = (int)(e % k);
+      const int a = (int)((e / k) % dl);
+      const int s = (int)(e / ((int64_t)k * dl));
+      v = Wn[(int64_t)j * ldx + s * dl + a];
+    } else {
+      const int b = (int)(e % dr);
+      const int j = (int)((e / dr) % k);
+      const int s = (int)(e / ((int64_t)dr * k));
+      v = Wn[(int64_t)j * ldx + s * dr + b];
+      v.y = -v.y;
+    }
+    A[e] = v;
+  }
+}
+
+// Absorb the non-orthonormal factor into the neighbour, batched over s.
+//  right: out[s][j][c] = sum_b P[j][b] A[s][b][c]   (P: k x db)
+//  left:  out[s][a][j] = sum_b A[s][a][b] conj P[j][b]
+__global__ __launch_bounds__(GT_THREADS) void k_absorb(const double2* P, int pld, const double2* A,
+                                                      int da, int db, int k, int right,
+                                                      double2* out) {
+  __shared__ SmemC64 sm;
+  const int s = blockIdx.z;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  AccC64 acc;
+  acc_zero(acc);
+  if (right) {
+    // A here is (db x da) per s: rows b, cols c
+    const double2* a = A + (int64_t)s * db * da;
+    auto fa = [&](int m, int kk) -> double2 { return P[(int64_t)m * pld + kk]; };
+    auto fb = [&](int kk, int n) -> double2 { return a[(int64_t)kk * da + n]; };
+    LoadA<decltype(fa), true> la{fa, m0, k, db};
+    LoadB<decltype(fb), true> lb{fb, n0, db, da};
+    cgemm_mainloop(la, lb, db, sm, acc);
+    double2* o = out + (int64_t)s * k * da;
+    acc_foreach(acc, [&](int r, int c, double re, double im) {
+      int m = m0 + r, n = n0 + c;
+      if (m < k && n < da) o[(int64_t)m * da + n] = make_double2(re, im);
+    });
+  } else {
+    // A is (da x db) per s: rows a, cols b
+    const double2* a = A + (int64_t)s * da * db;
+    auto fa = [&](int m, int kk) -> double2 { return a[(int64_t)m * db + kk]; };
+    auto fb = [&](int kk, int n) -> double2 {
+      double2 v = P[(int64_t)n * pld + kk];
+      return make_double2(v.x, -v.y);
+    };
+    LoadA<decltype(fa), true> la{fa, m0, da, db};
+    LoadB<decltype(fb), false> lb{fb, n0, db, k};
+    cgemm_mainloop(la, lb, db, sm, acc);
+    double2* o = out + (int64_t)s * da * k;
+    acc_foreach(acc, [&](int r, int c, double re, double im) {
+      int m = m0 + r, n = n0 + c;
+      if (m < da && n < k) o[(int64_t)m * k + n] = make_double2(re, im);
+    });
+  }
+}
+
+__global__ void k_normalize_site(double2* A, int64_t cnt, double* norm_out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) s += A[e].x * A[e].x + A[e].y * A[e].y;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  const double inv = 1.0 / nrm;
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) A[e] = make_double2(A[e].x * inv, A[e].y * inv);
+  if (threadIdx.x == 0) *norm_out = nrm;
+}
+
+// ------------------------------------------------------------ workspace
+struct BuildWork {
+  DevBuf T, X, X0, Wn, P, jac, sigma, sorted, order, scal, rot;
+  RankOut* host_rank = nullptr;   // pinned
+  int* host_rot = nullptr;        // pinned
+  BuildWork() {
+    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&host_rank), sizeof(RankOut)));
+    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&host_rot), sizeof(int)));
+  }
+  ~BuildWork() {
+    if (host_rank) (void)hipHostFree(host_rank);
+    if (host_rot) (void)hipHostFree(host_rot);
+  }
+};
+
+static int grid1d(int64_t n, int per = 256) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65535));
+}
+
+// Orthogonalise X (len x cnt) and produce Wn (k columns) and P (k x cnt).
+struct SplitResult {
+  int k, nnz, sweeps;
+  double eps_step, w, nrm;
+};
+
+static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl, int cap,
+                             double eps, bool renorm, std::vector<double>* spectrum_out) {
+  hipStream_t s = st.stream;
+  double2* X = ws.X.as<double2>();
+  int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, 1.0, s, 60);
+  st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
+  hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  RCS_REQUIRE(pl.cnt <= SORT_MAX, "matrix too wide for the rank kernel");
+  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, cap, eps,
+                     ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>());
+  HIP_LAUNCH_OK();
+  HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const RankOut r = *ws.host_rank;
+  if (r.bad) fail(RCS_ERR_NUMERIC, "non-finite singular values");
+  SplitResult out{r.k, r.nnz, sweeps, r.eps_step, r.w, r.nrm};
+  if (spectrum_out) {
+    spectrum_out->resize(pl.cnt);
+    HIP_OK(hipMemcpyAsync(spectrum_out->data(), ws.sorted.p, pl.cnt * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(pl.ldx, 256), out.k), dim3(256), 0, s, X, pl.ldx,
+                     ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
+  HIP_LAUNCH_OK();
+  const double scale = renorm ? 1.0 / out.nrm : 1.0;
+  hipLaunchKernelGGL(k_project, dim3(ceil_div(pl.cnt, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
+                     ws.Wn.as<double2>(), ws.X0.as<double2>(), pl.ldx, pl.len, out.k, pl.cnt, scale,
+                     ws.P.as<double2>());
+  HIP_LAUNCH_OK();
+  return out;
+}
+
+static void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
+  const size_t xbytes = (size_t)pl.ldx * pl.cnt_pad * sizeof(double2);
+  ws.X.ensure(xbytes);
+  ws.X0.ensure(xbytes);
+  ws.Wn.ensure(xbytes);
+  ws.P.ensure((size_t)pl.cnt_pad * pl.cnt_pad * sizeof(double2) + (size_t)pl.ldx * pl.cnt * sizeof(double2));
+  ws.jac.ensure(jacobi_work_bytes(pl));
+  ws.sigma.ensure((size_t)pl.cnt_pad * sizeof(double));
+  ws.sorted.ensure((size_t)pl.cnt_pad * sizeof(double));
+  ws.order.ensure((size_t)pl.cnt_pad * sizeof(int));
+  ws.scal.ensure(sizeof(RankOut));
+  ws.rot.ensure(sizeof(int));
+  if (t_elems > 0) ws.T.ensure((size_t)t_elems * sizeof(double2));
+}
+
+// Move the orthogonality centre one step (exact orthogonalisation by SVD,
+// dropping only exact zeros).
+static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
+  hipStream_t s = st.stream;
+  const int c = st.center;
+  const int dl = st.dims[c], dr = st.dims[c + 1];
+  const int len = right ? 2 * dl : 2 * dr;
+  const int cnt = right ? dr : dl;
+  JacobiPlan pl = jacobi_plan(len, cnt);
+  ensure_work(ws, pl, 0);
+  HIP_OK(hipMemsetAsync(ws.X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws.X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  hipLaunchKernelGGL(k_load_site, dim3(grid1d((int64_t)2 * dl * dr)), dim3(256), 0, s, st.site[c], dl, dr,
+                     right ? 1 : 0, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
+  HIP_LAUNCH_OK();
+  SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr);
+  const int k = r.k;
+  hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
+                     ws.Wn.as<double2>(), pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
+  HIP_LAUNCH_OK();
+  if (right) {
+    const int d2 = st.dims[c + 2];
+    hipLaunchKernelGGL(k_absorb, dim3(ceil_div(d2, GT_N), ceil_div(k, GT_M), 2), dim3(GT_THREADS), 0, s,
+                       ws.P.as<double2>(), pl.cnt, st.site[c + 1], d2, dr, k, 1, st.spare_ptr);
+    HIP_LAUNCH_OK();
+    std::swap(st.site[c + 1], st.spare_ptr);
+    st.dims[c + 1] = k;
+    st.center = c + 1;
+  } else {
+    const int d0 = st.dims[c - 1];
+    hipLaunchKernelGGL(k_absorb, dim3(ceil_div(k, GT_N), ceil_div(d0, GT_M), 2), dim3(GT_THREADS), 0, s,
+                       ws.P.as<double2>(), pl.cnt, st.site[c - 1], d0, dl, k, 0, st.spare_ptr);
+    HIP_LAUNCH_OK();
+    std::swap(st.site[c - 1], st.spare_ptr);
+    st.dims[c] = k;
+    st.center = c - 1;
+  }
+}
+
+static void two_site_update(rcs_state_s& st, BuildWork& ws, int i, const double2* gate16, int cap,
+                            double eps, int prefer_left, int cycle, bool log_spectra) {
+  hipStream_t s = st.stream;
+  while (st.center < i) move_center(st, ws, true);
+  while (st.center > i + 1) move_center(st, ws, false);
+  const int dl = st.dims[i], dm = st.dims[i + 1], dr = st.dims[i + 2];
+  int orient;
+  if (dr < dl)
+    orient = 1;
+  else if (dl < dr)
+    orient = 2;
+  else
+    orient = prefer_left ? 2 : 1;
+  const int len = orient == 1 ? 2 * dl : 2 * dr;
+  const int cnt = orient == 1 ? 2 * dr : 2 * dl;
+  JacobiPlan pl = jacobi_plan(len, cnt);
+  ensure_work(ws, pl, (int64_t)4 * dl * dr);
+  // T = the four products
+  hipLaunchKernelGGL(k_two_site_f64, dim3(ceil_div(dr, GT_N), ceil_div(dl, GT_M), 4), dim3(GT_THREADS), 0, s,
+                     st.site[i], st.site[i + 1], ws.T.as<double2>(), dl, dm, dr);
+  HIP_LAUNCH_OK();
+  HIP_OK(hipMemsetAsync(ws.X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws.X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  Gate4 G;
+  for (int e = 0; e < 16; ++e) G.g[e] = gate16[e];
+  hipLaunchKernelGGL(k_mix_gate, dim3(grid1d((int64_t)dl * dr)), dim3(256), 0, s, ws.T.as<double2>(), G, dl,
+                     dr, orient, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
+  HIP_LAUNCH_OK();
+  std::vector<double> spec;
+  SplitResult r = svd_split(st, ws, pl, std::min(cap, st.cap[i + 1]), eps, true,
+                            log_spectra ? &spec : nullptr);
+  const int k = r.k;
+  hipLaunchKernelGGL(k_write_split, dim3(grid1d((int64_t)2 * k * (dl + dr))), dim3(256), 0, s,
+                     ws.Wn.as<double2>(), pl.ldx, ws.P.as<double2>(), pl.cnt, k, dl, dr, orient,
+                     st.site[i], st.site[i + 1]);
+  HIP_LAUNCH_OK();
+  st.dims[i + 1] = k;
+  st.center = orient == 1 ? i + 1 : i;
+  st.log_fest += std::log1p(-r.eps_step);
+  st.sum_eps += r.eps_step;
+  st.n_trunc += 1;
+  if (log_spectra) {
+    SpectrumRecord rec;
+    rec.pos = i;
+    rec.cycle = cycle;
+    rec.m = cnt;
+    rec.kept = k;
+    rec.chi_l = dl;
+    rec.chi_r = dr;
+    rec.values = std::move(spec);
+    st.spectra.push_back(std::move(rec));
+  }
+}
+
+static void apply_layer(rcs_state_s& st, const rcs_circuit_s& c, int layer) {
+  Layer1q L;
+  int64_t mx = 1;
+  for (int k = 0; k < st.n; ++k) {
+    L.site[k] = st.site[k];
+    L.dl[k] = st.dims[k];
+    L.dr[k] = st.dims[k + 1];
+    L.gate[k] = (uint8_t)c.layers_1q[layer][st.pi[k]];
+    mx = std::max<int64_t>(mx, (int64_t)L.dl[k] * L.dr[k]);
+  }
+  hipLaunchKernelGGL(k_apply_1q, dim3(grid1d(mx), st.n), dim3(256), 0, st.stream, L);
+  HIP_LAUNCH_OK();
+}
+
+static void upload_gates_once() {
+  static bool done = false;
+  if (done) return;
+  double2 g[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int e = 0; e < 4; ++e) {
+      auto v = one_qubit_gate(i)[e];
+      g[i][e] = make_double2(v.real(), v.imag());
+    }
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_gates1q), g, sizeof(g)));
+  done = true;
+}
+
+void canonicalize(rcs_state_s& st, BuildWork& ws) {
+  while (st.center > 0) move_center(st, ws, false);
+  DevBuf nrm;
+  nrm.ensure(sizeof(double));
+  hipLaunchKernelGGL(k_normalize_site, dim3(1), dim3(256), 0, st.stream, st.site[0],
+                     (int64_t)2 * st.dims[0] * st.dims[1], nrm.as<double>());
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(st.stream));
+  st.canonical = true;
+}
+
+void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, const BuildOptions& o,
+               BuildWork& ws) {
+  upload_gates_once();
+  jacobi_init_attributes();
+  RCS_REQUIRE(c.n <= 64, "too many qubits");
+  st.pi = c.snake;
+  std::array<double2, 16> fs, sw;
+  auto sg = swap_gate();
+  for (int e = 0; e < 16; ++e) {
+    fs[e] = make_double2(c.fsim[e].real(), c.fsim[e].imag());
+    sw[e] = make_double2(sg[e].real(), sg[e].imag());
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  HIP_OK(hipEventRecord(e0, st.stream));
+  st.canonical = false;
+  const int nops = (int)c.ops.size();
+  const int stop = (o.max_ops < 0) ? nops : std::min(nops, o.max_ops);
+  for (int oi = 0; oi < stop; ++oi) {
+    const Op& op = c.ops[oi];
+    if (op.kind == 0) {
+      apply_layer(st, c, op.arg);
+      continue;
+    }
+    // where does the next update want the centre?
+    int prefer_left = 0;
+    for (int nj = oi + 1; nj < nops; ++nj)
+      if (c.ops[nj].kind == 1) {
+        prefer_left = c.ops[nj].arg < op.arg ? 1 : 0;
+        break;
+      }
+    two_site_update(st, ws, op.arg, op.gate == 0 ? fs.data() : sw.data(), chi, eps, prefer_left,
+                    op.cycle, o.log_spectra);
+    if (op.gate == 1) std::swap(st.pi[op.arg], st.pi[op.arg + 1]);
+  }
+  if (o.canonicalize) canonicalize(st, ws);
+  HIP_OK(hipEventRecord(e1, st.stream));
+  HIP_OK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  st.build_seconds = ms * 1e-3;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+void build_dispatch(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps,
+                    const BuildOptions& o, BuildWork& ws) {
+  RCS_REQUIRE(o.contraction == RCS_PREC_C128 && o.rank_mode == RCS_RANK_FULL_SVD,
+              "precision/rank mode not available yet");
+  build_one(st, c, chi, eps, o, ws);
+}
+
+BuildWork* new_work() { return new BuildWork(); }
+void delete_work(BuildWork* w) { delete w; }
+
+}  // namespace rcs
+
+// ------------------------------------------------------------------ C ABI
+#define RCS_API_BEGIN try {
+#define RCS_API_END                                   \
+  }                                                   \
+  catch (const rcs::Error& e) {                       \
+    rcs::set_last_error(e.what());                    \
+    return e.status;                                  \
+  }                                                   \
+  catch (const std::exception& e) {                   \
+    rcs::set_last_error(e.what());                    \
+    return RCS_ERR_DEVICE;                            \
+  }                                                   \
+  return RCS_OK;
+
+extern "C" {
+
+void rcs_build_opts_default(rcs_build_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->contraction = RCS_PREC_C128;
+  o->rank_mode = RCS_RANK_FULL_SVD;
+  o->fallback_tau = 1e-6;
+  o->rsvd_oversample = 16;
+  o->rsvd_power_iters = 2;
+  o->rsvd_seed = 0x5eed;
+  o->max_ops = -1;
+  o->canonicalize = 1;
+}
+
+static rcs::BuildOptions to_options(const rcs_build_opts* opts) {
+  rcs_build_opts d;
+  rcs_build_opts_default(&d);
+  const rcs_build_opts& o = opts ? *opts : d;
+  rcs::BuildOptions b;
+  RCS_REQUIRE(o.contraction >= 0 && o.contraction <= 2, "bad contraction precision");
+  RCS_REQUIRE(o.rank_mode >= 0 && o.rank_mode <= 2, "bad rank mode");
+  b.contraction = o.contraction;
+  b.rank_mode = o.rank_mode;
+  b.fallback_tau = o.fallback_tau;
+  if (o.mlp_weights_host && o.mlp_count > 0)
+    b.mlp.assign(o.mlp_weights_host, o.mlp_weights_host + o.mlp_count);
+  b.rsvd_p = o.rsvd_oversample;
+  b.rsvd_q = o.rsvd_power_iters;
+  b.rsvd_seed = o.rsvd_seed;
+  b.stream = o.stream;
+  b.log_spectra = o.log_spectra != 0;
+  b.max_ops = o.max_ops;
+  b.canonicalize = o.canonicalize != 0;
+  if (b.rank_mode == RCS_RANK_LEARNED)
+    RCS_REQUIRE((int64_t)b.mlp.size() == RCS_MLP_PARAMS, "learned mode needs the packed network weights");
+  return b;
+}
+
+rcs_status rcs_build_state_ex(rcs_circuit circuit, int32_t chi, double trunc_eps,
+                              const rcs_build_opts* opts, rcs_state* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(circuit && out, "null argument");
+  *out = nullptr;
+  RCS_REQUIRE(chi >= 1 && chi <= 2048, "chi must be in [1, 2048]");
+  RCS_REQUIRE(trunc_eps >= 0.0 && trunc_eps < 1.0, "trunc_eps must be in [0, 1)");
+  rcs::BuildOptions b = to_options(opts);
+  auto st = std::make_unique<rcs_state_s>();
+  st->stream = rcs::as_stream(b.stream);
+  HIP_OK(hipGetDevice(&st->device));
+  rcs::state_alloc(*st, circuit->n, chi);
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  rcs::build_dispatch(*st, *circuit, chi, trunc_eps, b, *ws);
+  *out = st.release();
+  RCS_API_END
+}
+
+rcs_status rcs_build_state(rcs_circuit circuit, int32_t chi, double trunc_eps, rcs_state* out) {
+  return rcs_build_state_ex(circuit, chi, trunc_eps, nullptr, out);
+}
+
+rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, const double* eps,
+                           int32_t n, const rcs_build_opts* opts, rcs_state* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(circuits && chi && eps && out && n >= 0, "null argument");
+  for (int i = 0; i < n; ++i) out[i] = nullptr;
+  rcs::BuildOptions b = to_options(opts);
+  std::vector<std::unique_ptr<rcs_state_s>> states;
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  for (int i = 0; i < n; ++i) {
+    RCS_REQUIRE(circuits[i], "null circuit in batch");
+    RCS_REQUIRE(chi[i] >= 1 && chi[i] <= 2048, "chi must be in [1, 2048]");
+    RCS_REQUIRE(eps[i] >= 0.0 && eps[i] < 1.0, "eps must be in [0, 1)");
+    auto st = std::make_unique<rcs_state_s>();
+    st->stream = rcs::as_stream(b.stream);
+    HIP_OK(hipGetDevice(&st->device));
+    rcs::state_alloc(*st, circuits[i]->n, chi[i]);
+    rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], b, *ws);
+    states.push_back(std::move(st));
+  }
+  for (int i = 0; i < n; ++i) out[i] = states[i].release();
+  RCS_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Shot sampler, amplitude evaluator and linear-XEB reduction.
+//
+// Sampling (Section 3.2, stage 3) from a right-canonical MPS: for a batch of
+// S shots the partial amplitude vectors v (one row per shot) advance site by
+// site:  W^s = V A_k^s  (s = 0, 1), a complex GEMM with the shots as the M
+// dimension so that every site tensor is streamed once per batch and reused
+// by all S shots on the matrix cores.  The GEMM epilogue reduces |W^s|^2 per
+// shot over its 64 columns (fixed-order tree), and a per-shot decision step
+// sums the column-tile partials in fixed order, draws u from Philox, picks
+// the branch and records the bit.  The next site reads its V rows straight
+// out of W at the chosen half (no copy).  The last site has a single column,
+// whose |w|^2 is p(b).
+#include "gemm_f64.h"
+#include "state.h"
+
+namespace rcs {
+
+struct ChainArgs {
+  const double2* wprev;  // S x 2*dl from the previous site (null at site 0)
+  const int8_t* sel;     // per-shot chosen half at the previous site
+  const double2* site;   // A_k, [s][a][b], dl x dr
+  double2* wout;         // S x 2*dr
+  double* part;          // [2][S][ntiles] partial |w|^2
+  int S, dl, dr, ntiles;
+};
+
+__global__ __launch_bounds__(GT_THREADS) void k_chain_gemm(ChainArgs a) {
+  __shared__ SmemC64 sm;
+  __shared__ double rowsum[2][GT_M];
+  const int tn = blockIdx.x, tm = blockIdx.y, s = blockIdx.z;
+  const int m0 = tm * GT_M, n0 = tn * GT_N;
+  const int dl = a.dl, dr = a.dr;
+  auto fa = [&](int m, int k) -> double2 {
+    if (a.wprev == nullptr) return (k == 0) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+    return a.wprev[(int64_t)m * 2 * dl + (int64_t)a.sel[m] * dl + k];
+  };
+  const double2* bs = a.site + (int64_t)s * dl * dr;
+  auto fb = [&](int k, int n) -> double2 { return bs[(int64_t)k * dr + n]; };
+  LoadA<decltype(fa), true> la{fa, m0, a.S, dl};
+  LoadB<decltype(fb), true> lb{fb, n0, dl, dr};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, dl, sm, acc);
+
+  // store W and reduce |w|^2 per row over this tile's columns
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  double rs[2][4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rs[mt][r] = 0.0;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = m0 + wm + mt * 16 + f64_row(lane, r);
+        int n = n0 + wn + nt * 16 + (lane & 15);
+        double re = acc.re[mt][nt][r], im = acc.im[mt][nt][r];
+        if (m < a.S && n < dr) {
+          a.wout[(int64_t)m * 2 * dr + (int64_t)s * dr + n] = make_double2(re, im);
+          rs[mt][r] += re * re + im * im;
+        }
+      }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = rs[mt][r];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if ((lane & 15) == 0) rowsum[w >> 1][wm + mt * 16 + f64_row(lane, r)] = v;
+    }
+  __syncthreads();
+  if (tid < GT_M) {
+    int m = m0 + tid;
+    if (m < a.S) a.part[((int64_t)s * a.S + m) * a.ntiles + tn] = rowsum[0][tid] + rowsum[1][tid];
+  }
+}
+
+struct DecideArgs {
+  const double* part;
+  int S, ntiles, site, qubit, last, mode;
+  uint64_t seed, shot0;
+  int8_t* sel;
+  uint64_t* bits;          // mode 0 output
+  double* log2p;           // mode 0 output (nullable)
+  const uint64_t* inbits;  // mode 1 input
+  const double2* wlast;    // S x 2 at the last site
+  double2* amps;           // mode 1 output
+};
+
+__global__ void k_decide(DecideArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.S) return;
+  if (a.mode == 0) {
+    double p0 = 0.0, p1 = 0.0;
+    const double* q0 = a.part + (int64_t)m * a.ntiles;
+    const double* q1 = a.part + ((int64_t)a.S + m) * a.ntiles;
+    for (int t = 0; t < a.ntiles; ++t) {
+      p0 += q0[t];
+      p1 += q1[t];
+    }
+    const double u = shot_uniform(a.seed, a.shot0 + (uint64_t)m, a.site);
+    const int b = (u * (p0 + p1) >= p0) ? 1 : 0;
+    const uint64_t bit = (uint64_t)b << a.qubit;
+    a.bits[m] = (a.site == 0) ? bit : (a.bits[m] | bit);
+    a.sel[m] = (int8_t)b;
+    if (a.last && a.log2p) a.log2p[m] = log2(b ? p1 : p0);
+  } else {
+    const int b = (int)((a.inbits[m] >> a.qubit) & 1ull);
+    a.sel[m] = (int8_t)b;
+    if (a.last) a.amps[m] = a.wlast[(int64_t)m * 2 + b];
+  }
+}
+
+void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed, int mode,
+               uint64_t* bits_dev, double* log2p_dev, const uint64_t* in_bits_dev,
+               double* amps_dev) {
+  if (n_shots == 0) return;
+  int maxd = 1;
+  for (int d : st.dims) maxd = std::max(maxd, d);
+  int64_t smax = (int64_t(1) << 30) / (2 * (int64_t)maxd * 16);
+  smax = std::max<int64_t>(64, std::min<int64_t>(65536, smax / 64 * 64));
+  const int64_t S0 = std::min<int64_t>(smax, (int64_t)round_up((int64_t)n_shots, 64));
+  const int ntiles_max = ceil_div(maxd, GT_N);
+  st.wbuf[0].ensure((size_t)S0 * 2 * maxd * sizeof(double2));
+  st.wbuf[1].ensure((size_t)S0 * 2 * maxd * sizeof(double2));
+  st.part.ensure((size_t)2 * S0 * ntiles_max * sizeof(double));
+  st.sel.ensure((size_t)S0);
+  for (uint64_t b0 = 0; b0 < n_shots; b0 += (uint64_t)S0) {
+    const int S = (int)std::min<uint64_t>((uint64_t)S0, n_shots - b0);
+    for (int k = 0; k < st.n; ++k) {
+      ChainArgs ca;
+      ca.wprev = (k == 0) ? nullptr : st.wbuf[(k - 1) & 1].as<double2>();
+      ca.sel = st.sel.as<int8_t>();
+      ca.site = st.site[k];
+      ca.wout = st.wbuf[k & 1].as<double2>();
+      ca.part = st.part.as<double>();
+      ca.S = S;
+      ca.dl = st.dims[k];
+      ca.dr = st.dims[k + 1];
+      ca.ntiles = ceil_div(ca.dr, GT_N);
+      dim3 grid(ca.ntiles, ceil_div(S, GT_M), 2);
+      hipLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, ca);
+      HIP_LAUNCH_OK();
+      DecideArgs da;
+      da.part = ca.part;
+      da.S = S;
+      da.ntiles = ca.ntiles;
+      da.site = k;
+      da.qubit = st.pi[k];
+      da.last = (k == st.n - 1);
+      da.mode = mode;
+      da.seed = seed;
+      da.shot0 = first_shot + b0;
+      da.sel = st.sel.as<int8_t>();
+      da.bits = bits_dev ? bits_dev + b0 : nullptr;
+      da.log2p = log2p_dev ? log2p_dev + b0 : nullptr;
+      da.inbits = in_bits_dev ? in_bits_dev + b0 : nullptr;
+      da.wlast = ca.wout;
+      da.amps = amps_dev ? reinterpret_cast<double2*>(amps_dev) + b0 : nullptr;
+      hipLaunchKernelGGL(k_decide, dim3(ceil_div(S, 256)), dim3(256), 0, st.stream, da);
+      HIP_LAUNCH_OK();
+    }
+  }
+}
+
+__global__ void k_abs2(const double2* z, uint64_t m, double* out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = z[i].x * z[i].x + z[i].y * z[i].y;
+}
+
+void abs2_to(const double2* z, uint64_t m, double* out, hipStream_t stream) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_abs2, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, z, m, out);
+  HIP_LAUNCH_OK();
+}
+
+// ------------------------------------------------------------------- XEB
+// Section 5.1: F = 2^n mean(p) - 1.  Two fixed-order passes (mean, then
+// squared deviations) over per-block partial sums; the host adds the block
+// partials in index order.
+constexpr int XEB_BLOCK = 256;
+constexpr int XEB_PER_THREAD = 16;
+
+__device__ inline double xeb_term(const double* v, uint64_t i, int nq, int is_log2) {
+  return is_log2 ? exp2(v[i] + (double)nq) : ldexp(v[i], nq);
+}
+
+__global__ void k_xeb_partial(const double* vals, uint64_t m, int nq, int is_log2, int pass,
+                              double mean, double* out) {
+  __shared__ double red[XEB_BLOCK];
+  const uint64_t base = (uint64_t)blockIdx.x * XEB_BLOCK * XEB_PER_THREAD;
+  double acc = 0.0;
+  for (int j = 0; j < XEB_PER_THREAD; ++j) {
+    uint64_t i = base + (uint64_t)j * XEB_BLOCK + threadIdx.x;
+    if (i < m) {
+      double x = xeb_term(vals, i, nq, is_log2);
+      acc += pass == 0 ? x : (x - mean) * (x - mean);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = XEB_BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+void xeb_reduce(int n_qubits, const double* vals_dev, uint64_t m, bool is_log2, double* xeb,
+                double* se, hipStream_t stream) {
+  RCS_REQUIRE(m >= 2, "need at least two samples");
+  RCS_REQUIRE(n_qubits >= 1 && n_qubits <= 64, "n_qubits out of range");
+  const uint64_t per = (uint64_t)XEB_BLOCK * XEB_PER_THREAD;
+  const int nb = (int)((m + per - 1) / per);
+  DevBuf part;
+  part.ensure((size_t)nb * sizeof(double));
+  std::vector<double> h(nb);
+  double sums[2] = {0.0, 0.0};
+  double mean = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_xeb_partial, dim3(nb), dim3(XEB_BLOCK), 0, stream, vals_dev, m, n_qubits,
+                       is_log2 ? 1 : 0, pass, mean, part.as<double>());
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(h.data(), part.p, nb * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(hipStreamSynchronize(stream));
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += h[i];
+    sums[pass] = s;
+    if (pass == 0) mean = s / (double)m;
+  }
+  *xeb = mean - 1.0;
+  *se = std::sqrt(sums[1] / (double)(m - 1)) / std::sqrt((double)m);
+}
+
+}  // namespace rcs

@@ -1,0 +1,106 @@
+"""GPU parity: state construction through the C-ABI against the dense state
+(exact builds) and the oracle MPS on the same schedule (truncated builds)."""
+import numpy as np
+import pytest
+
+from oracle import circuit as oc, dense, mps, sample
+from tests import inputs
+from tests.gpu_util import get_rcs, to_complex, normwise_rel, oracle_state_from, compare_shots
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    return get_rcs()
+
+
+def truncated_tolerance(om):
+    """Amplitude bar for a truncated fp64 build against the oracle.
+
+    A truncation keeps the span of the top-k singular vectors; a backward
+    error e in the two-site matrix rotates that span by about
+    e * s_k / (s_k - s_{k+1}) (first-order perturbation of singular
+    subspaces, Wedin 1972).  Both SVDs have e of order 1e-13 relative
+    (sqrt(m) u times the sweep count of a Jacobi or bidiagonal method), so the
+    bar is 1e-13 times the summed conditioning of the cuts, never below 1e-10.
+    """
+    kappa = 0.0
+    for rec in om.records:
+        s, k = rec["spectrum"], rec["k"]
+        if k < len(s) and s[k] > 1e-12 * s[0] and s[k - 1] > s[k]:
+            kappa += s[k - 1] / (s[k - 1] - s[k])
+    return max(1e-10, 1e-13 * kappa)
+
+
+def _amps(torch, g, b):
+    bits = torch.from_numpy(np.asarray(b).astype(np.int64)).cuda()
+    amps = torch.zeros(len(b), 2, dtype=torch.float64, device="cuda")
+    g.amplitudes(bits, amps)
+    return to_complex(amps)
+
+
+@pytest.mark.parametrize("rows,cols,cyc,seed", [(3, 4, 8, 1), (3, 4, 8, 7), (4, 4, 8, 2),
+                                                (2, 5, 6, 3)])
+def test_exact_build_equals_dense(env, rows, cols, cyc, seed):
+    rcs, torch = env
+    c = rcs.Circuit(rows, cols, cyc, seed)
+    g = rcs.State.build(c, 256, 0.0)
+    psi = dense.simulate(oc.Circuit(rows, cols, cyc, seed))
+    got = _amps(torch, g, np.arange(1 << c.n))
+    assert np.abs(got - psi).max() <= 1e-12 * 2.0 ** (-c.n / 2) * 10
+    assert normwise_rel(got, psi) < 1e-10
+    inf = g.info()
+    assert inf.canonical == 1 and inf.log_fidelity_est == 0.0
+    o = oracle_state_from(g.to_host())
+    assert o.canonical_residual() < 1e-12
+    om = mps.build(oc.Circuit(rows, cols, cyc, seed), 256, 0.0)
+    assert list(g.layout()[0]) == om.bond_dims()
+
+
+@pytest.mark.parametrize("rows,cols,cyc,seed,chi,eps", [(4, 5, 10, 3, 16, 1e-10),
+                                                        (3, 6, 12, 4, 12, 0.0),
+                                                        (4, 4, 10, 6, 8, 1e-6),
+                                                        (3, 7, 14, 8, 33, 1e-9)])
+def test_truncated_build_matches_oracle(env, rows, cols, cyc, seed, chi, eps):
+    rcs, torch = env
+    c = rcs.Circuit(rows, cols, cyc, seed)
+    g = rcs.State.build(c, chi, eps)
+    om = mps.build(oc.Circuit(rows, cols, cyc, seed), chi, eps)
+    b = inputs.random_bitstrings(c.n, 1000, seed=21)
+    got = _amps(torch, g, b)
+    ref = om.amplitudes(b)
+    assert normwise_rel(got, ref) < truncated_tolerance(om)
+    inf = g.info()
+    assert abs(inf.log_fidelity_est - om.log_fest) <= 1e-6 * max(1e-300, abs(om.log_fest)) + 1e-14
+    assert list(g.layout()[0]) == om.bond_dims()
+    assert inf.n_truncations == c.n_updates
+
+
+def test_shots_from_built_state(env):
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 10, 11)
+    g = rcs.State.build(c, 32, 1e-10)
+    o = oracle_state_from(g.to_host())
+    bits = torch.zeros(5000, dtype=torch.int64, device="cuda")
+    g.sample(bits, seed=4)
+    ob, _, tight = sample.sample(o, 5000, 4)
+    ok, n_exempt, n_diff = compare_shots(bits.cpu().numpy(), ob, tight)
+    assert ok and n_exempt == 0
+
+
+def test_build_is_deterministic(env):
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 8, 13)
+    a = rcs.State.build(c, 24, 1e-9).to_host()
+    b = rcs.State.build(c, 24, 1e-9).to_host()
+    assert all(np.array_equal(x, y) for x, y in zip(a[2], b[2]))
+
+
+def test_invalid_build_arguments(env):
+    rcs, torch = env
+    c = rcs.Circuit(3, 3, 2, 1)
+    for chi, eps in [(0, 0.0), (64, -1.0), (64, 1.0), (5000, 0.0)]:
+        with pytest.raises(rcs.RcsError) as ei:
+            rcs.State.build(c, chi, eps)
+        assert ei.value.status == 1

@@ -1,0 +1,88 @@
+"""Host-side checks (no GPU): the C-ABI library loads and exports every
+declared symbol; the C++ circuit generator and schedule compiler agree with
+the oracle's, op by op; argument validation."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.circuit import Circuit as OCircuit
+from oracle import mps as omps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rcs():
+    from paper_2512_07311_amd import build_lib
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build(verbose=False)
+    import paper_2512_07311_amd as m
+    return m
+
+
+def test_exports_every_declared_symbol(rcs):
+    hdr = open(os.path.join(ROOT, "include", "rcs.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(rcs_[a-z0-9_]+)\s*\(", hdr))
+    assert len(declared) >= 30
+    import ctypes
+    lib = ctypes.CDLL(rcs.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(rcs.EXPORTED)
+    assert "gfx950" in rcs.version()
+
+
+CONFIGS = [(3, 4, 8, 0), (5, 6, 14, 0), (6, 9, 14, 1), (6, 9, 20, 1), (4, 5, 3, 0), (2, 7, 9, 0)]
+
+
+@pytest.mark.parametrize("rows,cols,cyc,rr", CONFIGS)
+@pytest.mark.parametrize("seed", [1, 2, 12345678901234])
+def test_generator_and_schedule_match_oracle(rcs, rows, cols, cyc, rr, seed):
+    c = rcs.Circuit(rows, cols, cyc, seed, n_removed_random=rr)
+    o = OCircuit(rows, cols, cyc, seed, n_removed_random=rr)
+    assert c.n == o.n
+    assert np.array_equal(c.one_qubit_gates(), o.one_qubit_draws())
+    snake, ops = c.schedule()
+    pi, oops = omps.schedule(o)
+    assert list(snake) == pi
+    ref = []
+    for op in oops:
+        if op[0] == "1q":
+            ref.append((0, None, 0, op[2]))
+        else:
+            ref.append((1, op[1], 0 if op[2] == "fsim" else 1, op[3]))
+    assert len(ops) == len(ref)
+    for got, exp in zip(ops, ref):
+        assert got[0] == exp[0] and got[3] == exp[3]
+        if exp[0] == 1:
+            assert got[1] == exp[1] and got[2] == exp[2]
+    assert c.n_updates == sum(1 for r in ref if r[0] == 1)
+
+
+def test_explicit_removed_sites_and_pattern(rcs):
+    c = rcs.Circuit(4, 5, 6, 9, pattern="ACBD", removed=[0, 7])
+    o = OCircuit(4, 5, 6, 9, pattern="ACBD", removed=[0, 7])
+    assert c.n == o.n == 18
+    assert np.array_equal(c.one_qubit_gates(), o.one_qubit_draws())
+    assert list(c.schedule()[0]) == omps.schedule(o)[0]
+
+
+def test_c3_update_count(rcs):
+    c = rcs.Circuit(6, 9, 14, 1, n_removed_random=1)
+    assert c.n == 53 and c.n_updates == 2113
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(rows=1, cols=5, n_cycles=2, seed=1), "at least 2x2"),
+    (dict(rows=9, cols=9, n_cycles=2, seed=1), "qubits"),
+    (dict(rows=3, cols=3, n_cycles=2, seed=1, pattern="ABE"), "pattern"),
+    (dict(rows=3, cols=3, n_cycles=2, seed=1, removed=[9]), "out of range"),
+    (dict(rows=3, cols=3, n_cycles=-1, seed=1), "n_cycles"),
+])
+def test_invalid_arguments(rcs, kw, msg):
+    with pytest.raises(rcs.RcsError) as ei:
+        rcs.Circuit(**kw)
+    assert ei.value.status == 1 and msg in str(ei.value)
