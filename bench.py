@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the random-circuit-sampling hot path on one MI355X.
+
+One step = build the MPS output state of the 53-qubit (6x9 grid minus one
+seed-chosen site), 14-cycle ABCDCDAB circuit at bond cap chi = 1024, draw
+1,000,000 shots from it, and score them by linear XEB (self-XEB from the
+shots' own log2 probabilities).  `value` is the whole step's throughput in
+shots per second; the state-build seconds and the sampling rate are reported
+beside it.  Inputs (the circuit description, the shot buffers) are resident
+before the timed region starts.
+
+Forms: "plain" = complex128 contractions and the fp64 full SVD; "learned" =
+split-bf16 contractions, network-predicted ranks, fp32 randomized range
+finder with fp64 fall-back (weights from --mlp, or trained before the timed
+region on spectra of a differently seeded circuit).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form plain|learned]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="rcs53_6x9_c14_chi1024")
+    ap.add_argument("--shots", type=int, default=None)
+    ap.add_argument("--form", default="plain", choices=["plain", "learned"])
+    ap.add_argument("--mlp", default=None, help=".npy packed network weights (learned form)")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--profile-every", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-ops", type=int, default=-1, help="truncate the schedule (debugging only)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, seed, budget_s=20.0):
+    """The oracle (numpy fp64) timed on a bounded sample of the same workload:
+    saturated two-site updates (chi_l = chi_m = chi_r = chi) and sequential
+    chain-rule shots on an MPS with the workload's bond profile; scaled to
+    end-to-end shots/s for the full schedule and shot count."""
+    import numpy as np
+    from oracle import circuit as oc, mps, sample
+    from tests import inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    c = oc.Circuit(wl["rows"], wl["cols"], wl["cycles"], seed, n_removed_random=wl["removed_random"])
+    _, ops = mps.schedule(c)
+    n_upd = sum(1 for o in ops if o[0] == "u")
+    chi = wl["chi"]
+    # saturated updates
+    dims = [1] + [min(2 ** min(k, c.n - k), chi) for k in range(1, c.n)] + [1]
+    A = inputs.random_site_tensors(dims, seed=11)
+    st = mps.MPS(c.n, list(range(c.n)))
+    st.A = [a / np.sqrt(np.sum(np.abs(a) ** 2) / a.shape[0]) for a in A]
+    mid = c.n // 2
+    st.center = mid
+    t0 = time.time()
+    n_done = 0
+    while n_done < 2 and time.time() - t0 < budget_s * 0.6:
+        st.update(mid, c.gate2, chi, wl["eps"])
+        st.center = mid
+        n_done += 1
+    t_upd = (time.time() - t0) / n_done
+    # shots on a right-canonical state with the same bond profile
+    st2 = mps.MPS(c.n, list(range(c.n)))
+    st2.A = [a.copy() for a in A]
+    st2.center = c.n - 1
+    st2.right_canonicalize()
+    t1 = time.time()
+    n_sh = 0
+    while time.time() - t1 < budget_s * 0.4 or n_sh == 0:
+        sample.sample(st2, 4, seed=1003, first_shot=n_sh)
+        n_sh += 4
+    t_shot = (time.time() - t1) / n_sh
+    shots = wl["shots"]
+    total = n_upd * t_upd + shots * t_shot
+    return {"value": shots / total, "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": ("numpy fp64 oracle: %d saturated two-site updates (chi=%d, %.2f s each, x%d "
+                       "updates) + %d chain-rule shots (%.3f s each, x%d shots); extrapolated "
+                       "end-to-end" % (n_done, chi, t_upd, n_upd, n_sh, t_shot, shots))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2512_07311_amd as rcs
+    from tests import inputs
+    torch.cuda.set_device(0)
+    wl = dict(inputs.WORKLOADS[args.workload])
+    shots = args.shots or wl["shots"]
+    circ = rcs.Circuit(wl["rows"], wl["cols"], wl["cycles"], args.seed,
+                       n_removed_random=wl["removed_random"])
+    kw = dict(contraction="c128", rank_mode=0)
+    mlp_w = None
+    if args.form == "learned":
+        kw = dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6)
+        if args.mlp:
+            mlp_w = np.load(args.mlp).astype(np.float32)
+        else:
+            from paper_2512_07311_amd import learn
+            tr = inputs.WORKLOADS["rcs30_5x6_c14_chi256"]
+            tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1)
+            st = rcs.State.build(tc, tr["chi"], tr["eps"], log_spectra=True)
+            X, Y = learn.dataset(st.spectra(), tc.n, tr["cycles"], torch)
+            mlp_w, _ = learn.train(X, Y, torch, steps=1500, batch=256, seed=args.seed)
+            del st
+        kw["mlp_weights"] = mlp_w
+    bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
+    log2p = torch.zeros(shots, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st = rcs.State.build(circ, wl["chi"], wl["eps"], stream=stream, max_ops=args.max_ops, **kw)
+        t_b = time.time()
+        st.sample(bits, log2p, seed=1003)
+        x, se = rcs.xeb_log2(circ.n, log2p)
+        torch.cuda.synchronize()
+        return st, time.time() - t_b, x, se
+
+    for _ in range(args.warmup):
+        step()
+    rcs.profile_enable(args.profile_every)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    res = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.time()
+    prof = [rcs.profile_read(k) for k in range(len(rcs.KERNEL_CLASSES))]
+    rcs.profile_enable(0)
+    st, t_sample, xeb, se = res[-1]
+    inf = st.info()
+    sec = (t1 - t0) / args.steps
+    # dominant kernel: largest estimated total time (timed share scaled up)
+    est = [p["seconds"] * (p["launches"] / p["timed"]) if p["timed"] else 0.0 for p in prof]
+    dom = int(np.argmax(est))
+    p = prof[dom]
+    dt = {0: "fp64", 1: "fp64", 2: "fp64", 3: {"c128": "fp64", "c64": "fp32", "split_bf16": "bf16"}.get(
+        kw["contraction"], "fp64"), 4: "fp32"}[dom]
+    achieved = p["flops"] / p["seconds"] if p["seconds"] > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[dt] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAKS[dt], "traffic": None, "kernel": p["name"],
+            "avg_launch_us": 1e6 * p["seconds"] / max(p["timed"], 1),
+            "launches_per_step": p["launches"] // max(args.steps, 1),
+            "kernel_share_of_step": est[dom] / max(t1 - t0, 1e-9)}
+    out = {
+        "metric": "state-build s + shots/s per MI355X at chi=1024, learned/FP32 vs plain FP64, XEB",
+        "value": shots / sec, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.form == "plain" else "bf16x3/f32/f64",
+        "data": "synthetic (seeded random circuit)",
+        "config": {"workload": args.workload, "qubits": circ.n, "cycles": wl["cycles"], "chi": wl["chi"],
+                   "eps": wl["eps"], "shots": shots, "form": args.form, "contraction": kw["contraction"],
+                   "circuit_seed": args.seed, "max_ops": args.max_ops},
+        "state_build_s": inf.build_seconds, "sample_shots_per_s": shots / t_sample,
+        "self_xeb": xeb, "self_xeb_stderr": se, "log_fidelity_est": inf.log_fidelity_est,
+        "max_bond": inf.max_bond, "n_fallbacks": inf.n_fallbacks, "n_rsvd_accepted": inf.n_rsvd_accepted,
+        "roofline": roof,
+        "kernels": {q["name"]: {"launches": q["launches"], "timed": q["timed"],
+                                "avg_us": 1e6 * q["seconds"] / max(q["timed"], 1),
+                                "est_total_s": e} for q, e in zip(prof, est)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -252,6 +252,12 @@ rcs_status rcs_rsvd(int32_t len, int32_t cnt, const double* x_dev, int32_t l, in
 rcs_status rcs_spectrum_features(const double* s_dev, int32_t k, int32_t bond, int32_t n_sites,
                                  int32_t cycle, int32_t n_cycles, float* feat_dev, void* stream);
 
+/* Training targets of the rank network: 32 floats y_j = log10(max(tail(k_j)
+ * / w, 1e-20)), k_j = ceil(m j / 32), j = 1..32, for the full descending
+ * spectrum s_dev[0..m-1] (tail and w as in the rank rule, with the 1e-24
+ * zero floor). */
+rcs_status rcs_spectrum_targets(const double* s_dev, int32_t m, float* y_dev, void* stream);
+
 /* Rank network 66-128-128-32 (ReLU), fp32, packed weights W1,b1,W2,b2,W3,b3
  * (row-major W[out][in]).  Forward: out_dev[batch*32]. */
 #define RCS_MLP_PARAMS (66 * 128 + 128 + 128 * 128 + 128 + 128 * 32 + 32)
@@ -264,6 +270,20 @@ rcs_status rcs_mlp_backward(const float* w_dev, const float* x_dev, const float*
 rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float* v_dev,
                         int32_t count, int32_t step, float lr, float beta1, float beta2,
                         float eps, void* stream);
+
+/* ------------------------------------------------------------ measurement
+ * Sampled kernel timing for roofline reporting.  With every > 0, every
+ * every-th launch of each timed kernel class is bracketed by HIP events on
+ * the stream it runs on, together with the algorithmic flops and HBM bytes
+ * of that launch; every = 0 disables probing.  Both calls clear the
+ * counters.  Classes: 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram,
+ * 2 Jacobi rotation, 3 two-site contraction, 4 randomized range finder. */
+rcs_status rcs_profile_enable(int32_t every);
+/* Per class: launches seen, launches timed, summed seconds / flops / bytes of
+ * the timed launches.  Synchronises the pending events. */
+rcs_status rcs_profile_read(int32_t kclass, int64_t* launches, int64_t* timed, double* seconds,
+                            double* flops, double* bytes);
+const char* rcs_profile_class_name(int32_t kclass);
 
 /* ---------------------------------------------------------------- misc */
 const char* rcs_last_error(void);

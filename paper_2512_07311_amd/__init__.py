@@ -85,8 +85,11 @@ _SIGS = {
     "rcs_two_site": [_i32, _i32, _i32, _vp, _vp, _P(_d), _i32, _vp, _vp],
     "rcs_rsvd": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _P(_d), _vp],
     "rcs_spectrum_features": [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp],
+    "rcs_spectrum_targets": [_vp, _i32, _vp, _vp],
     "rcs_mlp_forward": [_vp, _vp, _i32, _vp, _vp],
     "rcs_mlp_backward": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "rcs_profile_enable": [_i32],
+    "rcs_profile_read": [_i32, _P(_i64), _P(_i64), _P(_d), _P(_d), _P(_d)],
     "rcs_mlp_adam": [_vp, _vp, _vp, _vp, _i32, _i32, C.c_float, C.c_float, C.c_float,
                      C.c_float, _vp],
 }
@@ -96,6 +99,8 @@ for _name, _args in _SIGS.items():
     _f.restype = C.c_int
 _lib.rcs_last_error.restype = C.c_char_p
 _lib.rcs_version.restype = C.c_char_p
+_lib.rcs_profile_class_name.argtypes = [_i32]
+_lib.rcs_profile_class_name.restype = C.c_char_p
 _lib.rcs_circuit_destroy.argtypes = [_vp]
 _lib.rcs_circuit_destroy.restype = None
 _lib.rcs_state_destroy.argtypes = [_vp]
@@ -104,7 +109,9 @@ _lib.rcs_build_opts_default.argtypes = [_P(BuildOpts)]
 _lib.rcs_build_opts_default.restype = None
 
 EXPORTED = sorted(list(_SIGS) + ["rcs_last_error", "rcs_version", "rcs_circuit_destroy",
-                                 "rcs_state_destroy", "rcs_build_opts_default"])
+                                 "rcs_state_destroy", "rcs_build_opts_default",
+                                 "rcs_profile_class_name"])
+KERNEL_CLASSES = ["k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder"]
 
 
 def _check(st):
@@ -347,6 +354,10 @@ def spectrum_features(s, k, bond, n_sites, cycle, n_cycles, feat, stream=None):
                                       _stream_ptr(stream)))
 
 
+def spectrum_targets(s, m, y, stream=None):
+    _check(_lib.rcs_spectrum_targets(_ptr(s), m, _ptr(y), _stream_ptr(stream)))
+
+
 def mlp_forward(w, x, out, stream=None):
     _check(_lib.rcs_mlp_forward(_ptr(w), _ptr(x), x.shape[0], _ptr(out), _stream_ptr(stream)))
 
@@ -359,3 +370,18 @@ def mlp_backward(w, x, y, grad, loss, stream=None):
 def mlp_adam(w, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_lib.rcs_mlp_adam(_ptr(w), _ptr(grad), _ptr(m), _ptr(v), w.numel(), step, lr, beta1,
                              beta2, eps, _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------- measurement
+def profile_enable(every):
+    _check(_lib.rcs_profile_enable(int(every)))
+
+
+def profile_read(kclass):
+    """dict(launches, timed, seconds, flops, bytes) of one kernel class."""
+    a, b = _i64(), _i64()
+    sec, fl, by = _d(), _d(), _d()
+    _check(_lib.rcs_profile_read(int(kclass), C.byref(a), C.byref(b), C.byref(sec), C.byref(fl),
+                                 C.byref(by)))
+    return dict(name=_lib.rcs_profile_class_name(int(kclass)).decode(), launches=a.value,
+                timed=b.value, seconds=sec.value, flops=fl.value, bytes=by.value)

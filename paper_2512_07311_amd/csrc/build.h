@@ -31,4 +31,13 @@ void build_dispatch(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps
 void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, const BuildOptions& o,
                BuildWork& ws);
 
+// Learned-rank network pieces (fp32).
+void spectrum_features(const double* s_dev, int k, int bond, int n_sites, int cycle, int n_cycles,
+                       float* feat_dev, hipStream_t st);
+void mlp_forward(const float* w, const float* x, int batch, float* out, float* act, hipStream_t s);
+
+// Reduced-precision two-site products (complex64 or split-bf16 on MFMA).
+void contract_two_site_lowp(const double2* A, const double2* B, double2* T, int dl, int dm, int dr,
+                            int precision, hipStream_t s);
+
 }  // namespace rcs

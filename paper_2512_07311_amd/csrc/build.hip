@@ -16,6 +16,7 @@
 // orthogonality centre where the next update needs it.
 #include <algorithm>
 #include <array>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 
@@ -23,6 +24,8 @@
 #include "circuit.h"
 #include "gemm_f64.h"
 #include "jacobi.h"
+#include "prof.h"
+#include "rsvd.h"
 #include "state.h"
 
 namespace rcs {
@@ -107,6 +110,19 @@ __global__ __launch_bounds__(GT_THREADS) void k_two_site_f64(const double2* A, c
     int m = m0 + r, n = n0 + c;
     if (m < dl && n < dr) t[(int64_t)m * dr + n] = make_double2(re, im);
   });
+}
+
+// T = the four products A^{s1'} B^{s2'} in the requested contraction precision.
+void contract_two_site(const double2* A, const double2* B, double2* T, int dl, int dm, int dr, int precision,
+                       hipStream_t s) {
+  Probe pr(kKcTwoSite, s, 32.0 * dl * (double)dm * dr, 16.0 * (2.0 * dl * dm + 2.0 * dm * dr + 4.0 * dl * dr));
+  if (precision != RCS_PREC_C128) {
+    contract_two_site_lowp(A, B, T, dl, dm, dr, precision, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_two_site_f64, dim3(ceil_div(dr, GT_N), ceil_div(dl, GT_M), 4), dim3(GT_THREADS), 0, s, A, B,
+                     T, dl, dm, dr);
+  HIP_LAUNCH_OK();
 }
 
 struct Gate4 {
@@ -195,6 +211,29 @@ __global__ void k_colnorm(const double2* X, int ldx, int len, double* sigma) {
   if (threadIdx.x == 0) sigma[j] = sqrt(red[0]);
 }
 
+// Permute columns of X (len x cnt) into Xs by descending norm (order from
+// k_sort_rank); sorted columns converge faster under cyclic Jacobi.
+__global__ void k_permute_cols(const double2* X, int ldx, int len, const int* order, double2* Xs) {
+  const int j = blockIdx.y;
+  const double2* src = X + (int64_t)order[j] * ldx;
+  double2* dst = Xs + (int64_t)j * ldx;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < len; r += gridDim.x * blockDim.x) dst[r] = src[r];
+}
+
+// *out = sum of squares of v[0..n) (fixed-order tree)
+__global__ void k_sum_sq(const double* v, int n, double* out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m += v[i] * v[i];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 // Sort sigma descending (ties by index), apply the rank rule.
 //  w = sum s^2; s^2 <= 1e-24 w counts as zero; tail(k) = sum_{r>=k} s_r^2
 //  from the smallest upward; k_eps = min{k>=1 : tail(k) <= eps w};
@@ -210,7 +249,7 @@ constexpr int SORT_MAX = 4096;
 
 __global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt, int cap,
                                                    double eps, double* sorted, int* order,
-                                                   RankOut* out) {
+                                                   RankOut* out, const double* extra_tail) {
   __shared__ double key[SORT_MAX];
   __shared__ int idx[SORT_MAX];
   int npow = 1;
@@ -247,7 +286,9 @@ __global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt
     order[i] = idx[i];
   }
   if (threadIdx.x == 0) {
-    double w = 0.0;
+    // extra: discarded weight that lies outside the decomposed subspace
+    const double extra = extra_tail ? fmax(*extra_tail, 0.0) : 0.0;
+    double w = extra;
     int bad = 0;
     for (int i = cnt - 1; i >= 0; --i) {
       double v = key[i];
@@ -260,7 +301,7 @@ __global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt
       if (key[i] * key[i] > floor) nnz = i + 1;
     // tail sums from the smallest upward; find the smallest k >= 1 with
     // tail(k) <= eps w by scanning k downward while the condition holds.
-    double tail = 0.0;
+    double tail = extra;
     int k_eps = cnt;
     double tail_at[1];
     (void)tail_at;
@@ -279,7 +320,7 @@ __global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt
       tail += (v2 <= floor) ? 0.0 : v2;
     }
     int k = min(k_eps, cap);
-    double tk = 0.0;
+    double tk = extra;
     if (k == k_eps) {
       tk = tail_k;
     } else {
@@ -310,6 +351,48 @@ __global__ void k_gather_normalize(const double2* X, int ldx, const int* order, 
     double2 v = src[r];
     dst[r] = make_double2(v.x * inv, v.y * inv);
   }
+}
+
+// Newton-Schulz orthonormalisation of the kept columns (the Jacobi stops at
+// an absolute floor, so columns of small singular values are orthonormal
+// only to ~floor / (s_i s_j)):  Wn <- Wn (3 I - Wn^H Wn) / 2.
+// H (k x k, row-major) = (3 I - Wn^H Wn) / 2
+__global__ __launch_bounds__(GT_THREADS) void k_ns_gram(const double2* Wn, int ldx, int len, int k,
+                                                       double2* H) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int kk) -> double2 {
+    double2 v = Wn[(int64_t)m * ldx + kk];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int kk, int n) -> double2 { return Wn[(int64_t)n * ldx + kk]; };
+  LoadA<decltype(fa), true> la{fa, m0, k, len};
+  LoadB<decltype(fb), false> lb{fb, n0, len, k};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, len, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    int m = m0 + r, n = n0 + c;
+    if (m < k && n < k) H[(int64_t)m * k + n] = make_double2(((m == n) ? 1.5 : 0.0) - 0.5 * re, -0.5 * im);
+  });
+}
+
+// Out (len x k, column-major, ld ldx) = Wn H
+__global__ __launch_bounds__(GT_THREADS) void k_ns_apply(const double2* Wn, int ldx, int len, int k,
+                                                        const double2* H, double2* Out) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int kk) -> double2 { return Wn[(int64_t)kk * ldx + m]; };
+  auto fb = [&](int kk, int n) -> double2 { return H[(int64_t)kk * k + n]; };
+  LoadA<decltype(fa), false> la{fa, m0, len, k};
+  LoadB<decltype(fb), true> lb{fb, n0, k, k};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, k, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    int m = m0 + r, n = n0 + c;
+    if (m < len && n < k) Out[(int64_t)n * ldx + m] = make_double2(re, im);
+  });
 }
 
 // P (k x cnt, row-major) = scale * Wn^H X0
@@ -454,9 +537,50 @@ __global__ void k_normalize_site(double2* A, int64_t cnt, double* norm_out) {
   if (threadIdx.x == 0) *norm_out = nrm;
 }
 
+// Copy a column-major len x cnt matrix into the zero-padded Jacobi buffer.
+__global__ void k_copy_in(const double2* x, int len, int cnt, double2* X, int ldx) {
+  const int64_t tot = (int64_t)len * cnt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % len), c = (int)(e / len);
+    X[(int64_t)c * ldx + r] = x[e];
+  }
+}
+
+// s[j] = sorted[j]; u[:, j] = X[:, order[j]] / sorted[j] (0 when sorted[j] = 0)
+__global__ void k_copy_out(const double2* X, int ldx, int len, int cnt, const int* order,
+                           const double* sorted, double* s, double2* u) {
+  const int j = blockIdx.y;
+  const double sv = sorted[j];
+  const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s[j] = sv;
+  const double2* src = X + (int64_t)order[j] * ldx;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < len; r += gridDim.x * blockDim.x) {
+    double2 v = src[r];
+    u[(int64_t)j * len + r] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
+// Export layout (a, s, b) -> device layout [s][a][b]
+__global__ void k_to_device_layout(const double2* in, int da, int db, double2* out) {
+  const int64_t tot = (int64_t)2 * da * db;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e % db);
+    const int s = (int)((e / db) % 2);
+    const int a = (int)(e / (2 * (int64_t)db));
+    out[((int64_t)s * da + a) * db + b] = in[e];
+  }
+}
+
 // ------------------------------------------------------------ workspace
 struct BuildWork {
-  DevBuf T, X, X0, Wn, P, jac, sigma, sorted, order, scal, rot;
+  DevBuf T, X, X0, Wn, P, H, jac, sigma, sorted, order, scal, rot, tmp;
+  double2* wn_final = nullptr;   // orthonormal kept columns after svd_split
+  void* host_rank_dev() {
+    tmp.ensure(64);
+    return tmp.p;
+  }
   RankOut* host_rank = nullptr;   // pinned
   int* host_rot = nullptr;        // pinned
   BuildWork() {
@@ -469,8 +593,17 @@ struct BuildWork {
   }
 };
 
-static int grid1d(int64_t n, int per = 256) {
+int grid1d(int64_t n, int per = 256) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65535));
+}
+
+static bool sort_columns_first() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("RCS_JACOBI_SORT");
+    v = (e && e[0] == '0') ? 0 : 1;
+  }
+  return v == 1;
 }
 
 // Orthogonalise X (len x cnt) and produce Wn (k columns) and P (k x cnt).
@@ -480,16 +613,35 @@ struct SplitResult {
 };
 
 static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl, int cap,
-                             double eps, bool renorm, std::vector<double>* spectrum_out) {
+                             double eps, bool renorm, std::vector<double>* spectrum_out,
+                             const double* extra_dev = nullptr) {
   hipStream_t s = st.stream;
   double2* X = ws.X.as<double2>();
-  int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, 1.0, s, 60);
+  // ||X||_F^2 scales the Jacobi's numerically-zero column threshold
+  hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), pl.cnt,
+                     reinterpret_cast<double*>(ws.host_rank_dev()));
+  HIP_LAUNCH_OK();
+  HIP_OK(hipMemcpyAsync(&ws.host_rank->w, ws.host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const double fro2 = ws.host_rank->w;
+  if (sort_columns_first()) {
+    // order columns by norm (X0 keeps the original order for the projection)
+    hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, pl.cnt, 0.0,
+                       ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
+    HIP_LAUNCH_OK();
+    hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(pl.len, 256), pl.cnt), dim3(256), 0, s, ws.X0.as<double2>(),
+                       pl.ldx, pl.len, ws.order.as<int>(), X);
+    HIP_LAUNCH_OK();
+  }
+  int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
   st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
   hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
   RCS_REQUIRE(pl.cnt <= SORT_MAX, "matrix too wide for the rank kernel");
   hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, cap, eps,
-                     ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>());
+                     ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), extra_dev);
   HIP_LAUNCH_OK();
   HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -505,20 +657,29 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(pl.ldx, 256), out.k), dim3(256), 0, s, X, pl.ldx,
                      ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
   HIP_LAUNCH_OK();
+  // orthonormalise: X <- Wn (3I - Wn^H Wn)/2 (X is free after the gather)
+  hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(out.k, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
+                     ws.Wn.as<double2>(), pl.ldx, pl.len, out.k, ws.H.as<double2>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(out.k, GT_N), ceil_div(pl.len, GT_M)), dim3(GT_THREADS), 0, s,
+                     ws.Wn.as<double2>(), pl.ldx, pl.len, out.k, ws.H.as<double2>(), X);
+  HIP_LAUNCH_OK();
+  ws.wn_final = X;
   const double scale = renorm ? 1.0 / out.nrm : 1.0;
   hipLaunchKernelGGL(k_project, dim3(ceil_div(pl.cnt, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
-                     ws.Wn.as<double2>(), ws.X0.as<double2>(), pl.ldx, pl.len, out.k, pl.cnt, scale,
+                     ws.wn_final, ws.X0.as<double2>(), pl.ldx, pl.len, out.k, pl.cnt, scale,
                      ws.P.as<double2>());
   HIP_LAUNCH_OK();
   return out;
 }
 
-static void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
+void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
   const size_t xbytes = (size_t)pl.ldx * pl.cnt_pad * sizeof(double2);
   ws.X.ensure(xbytes);
   ws.X0.ensure(xbytes);
   ws.Wn.ensure(xbytes);
   ws.P.ensure((size_t)pl.cnt_pad * pl.cnt_pad * sizeof(double2) + (size_t)pl.ldx * pl.cnt * sizeof(double2));
+  ws.H.ensure((size_t)pl.cnt_pad * pl.cnt_pad * sizeof(double2));
   ws.jac.ensure(jacobi_work_bytes(pl));
   ws.sigma.ensure((size_t)pl.cnt_pad * sizeof(double));
   ws.sorted.ensure((size_t)pl.cnt_pad * sizeof(double));
@@ -546,7 +707,7 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr);
   const int k = r.k;
   hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
-                     ws.Wn.as<double2>(), pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
+                     ws.wn_final, pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
   HIP_LAUNCH_OK();
   if (right) {
     const int d2 = st.dims[c + 2];
@@ -567,12 +728,148 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   }
 }
 
-static void two_site_update(rcs_state_s& st, BuildWork& ws, int i, const double2* gate16, int cap,
-                            double eps, int prefer_left, int cycle, bool log_spectra) {
+// Per-build state of the learned / randomized rank modes.
+struct UpdateCtx {
+  const BuildOptions* o = nullptr;
+  int n_cycles = 0;
+  int update_index = 0;
+  DevBuf w_mlp, feat, yhat, bond_spec, scal2;
+  std::vector<int> bond_k;          // kept count of each bond's last truncation
+  std::vector<double> prev_eps;     // discarded fraction of each bond's last truncation
+  RsvdWork rw;
+  DevBuf M;
+  int chi_cap = 0;
+  double* dev_scalars() { return scal2.as<double>(); }
+};
+
+__global__ void k_sub_scalar(const double* a, const double* b, double* out) { *out = *a - *b; }
+
+// k_hat = ceil(m f*), f* the first f where the interpolated prediction y(f)
+// drops to log10(eps) (y(0) = 0, knots at j/32); clamped to [1, min(cap, m)].
+static int predict_rank(const float* y, int m, int cap, double eps) {
+  const double target = eps > 0.0 ? std::log10(eps) : -20.0;
+  double fstar = 1.0, yprev = 0.0;
+  for (int j = 1; j <= 32; ++j) {
+    const double yj = y[j - 1];
+    if (yj <= target) {
+      const double f0 = (j - 1) / 32.0, f1 = j / 32.0;
+      fstar = (yj == yprev) ? f1 : f0 + (target - yprev) / (yj - yprev) * (f1 - f0);
+      break;
+    }
+    yprev = yj;
+  }
+  int k = (int)std::ceil(m * fstar - 1e-12);
+  return std::max(1, std::min({cap, k, m}));
+}
+
+static double predicted_eps(const float* y, int k, int m) {
+  const double f = (double)k / m;
+  const int j = std::min(31, (int)std::floor(f * 32.0));
+  const double f0 = j / 32.0, f1 = (j + 1) / 32.0;
+  const double y0 = j == 0 ? 0.0 : y[j - 1], y1 = y[j];
+  return std::pow(10.0, y0 + (f - f0) / (f1 - f0) * (y1 - y0));
+}
+
+static void record_bond_spectrum(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int i, int k) {
+  if (!ctx.o || ctx.o->rank_mode == RCS_RANK_FULL_SVD) return;
+  const int kk = std::min(k, ctx.chi_cap);
+  HIP_OK(hipMemcpyAsync(ctx.bond_spec.as<double>() + (size_t)i * ctx.chi_cap, ws.sorted.p, kk * sizeof(double),
+                        hipMemcpyDeviceToDevice, st.stream));
+  ctx.bond_k[i] = kk;
+}
+
+// Randomized split of the two-site matrix (T already holds the products).
+// Returns false when the randomized path does not apply or the judge rejects.
+static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int i, const double2* gate16,
+                             int cap, double eps, int cycle, bool log_spectra) {
+  hipStream_t s = st.stream;
+  const BuildOptions& o = *ctx.o;
+  const int dl = st.dims[i], dr = st.dims[i + 2];
+  const int len = 2 * dl, cnt = 2 * dr, m = std::min(len, cnt);
+  float y[32];
+  int k_hat;
+  if (o.rank_mode == RCS_RANK_LEARNED) {
+    spectrum_features(ctx.bond_spec.as<double>() + (size_t)i * ctx.chi_cap, ctx.bond_k[i], i, st.n, cycle,
+                      ctx.n_cycles, ctx.feat.as<float>(), s);
+    mlp_forward(ctx.w_mlp.as<float>(), ctx.feat.as<float>(), 1, ctx.yhat.as<float>(), nullptr, s);
+    HIP_OK(hipMemcpyAsync(y, ctx.yhat.p, sizeof(y), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    k_hat = predict_rank(y, m, cap, eps);
+  } else {
+    k_hat = std::min(cap, m);
+  }
+  const int l = std::min(k_hat + std::max(0, o.rsvd_p), m);
+  if (l >= m) return false;   // the sketch would cover the whole space: plain split
+  // M (len x cnt, column-major) from the products
+  const int ldm = (int)round_up(len, 64);
+  ctx.M.ensure((size_t)ldm * round_up(cnt, 64) * sizeof(double2));
+  double2* M = ctx.M.as<double2>();
+  Gate4 G;
+  for (int e = 0; e < 16; ++e) G.g[e] = gate16[e];
+  hipLaunchKernelGGL(k_mix_gate, dim3(grid1d((int64_t)dl * dr)), dim3(256), 0, s, ws.T.as<double2>(), G, dl, dr, 1,
+                     M, M, ldm);
+  HIP_LAUNCH_OK();
+  range_finder(M, ldm, len, cnt, l, std::max(0, o.rsvd_q), o.rsvd_seed, (uint64_t)ctx.update_index, ctx.rw, s);
+  JacobiPlan pl = jacobi_plan(cnt, l);
+  ensure_work(ws, pl, 0);
+  ws.sigma.ensure((size_t)std::max(cnt, pl.cnt_pad) * sizeof(double));
+  HIP_OK(hipMemsetAsync(ws.X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws.X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  project_to_basis(M, ldm, len, cnt, l, ctx.rw, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx, s);
+  // weight outside span(Q): ||M||_F^2 - ||B||_F^2 (fp64)
+  double* sc = ctx.dev_scalars();
+  hipLaunchKernelGGL(k_colnorm, dim3(cnt), dim3(256), 0, s, M, ldm, len, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), cnt, sc + 0);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_colnorm, dim3(l), dim3(256), 0, s, ws.X.as<double2>(), pl.ldx, cnt, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), l, sc + 1);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sub_scalar, dim3(1), dim3(1), 0, s, sc + 0, sc + 1, sc + 2);
+  HIP_LAUNCH_OK();
+  std::vector<double> spec;
+  SplitResult r = svd_split(st, ws, pl, cap, eps, true, log_spectra ? &spec : nullptr, sc + 2);
+  const double eps_pred = (o.rank_mode == RCS_RANK_LEARNED) ? predicted_eps(y, r.k, m) : ctx.prev_eps[i];
+  const bool accept = o.fallback_tau >= 0.0 && r.eps_step <= std::max(eps, eps_pred) + o.fallback_tau;
+  if (!accept) {
+    st.n_fallback += 1;
+    return false;
+  }
+  const int k = r.k;
+  // A_{i+1} = V_k^H (conjugated kept columns), A_i = Q (B V_k) / nrm
+  hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * dr)), dim3(256), 0, s, ws.wn_final, pl.ldx, k, dl,
+                     dr, 0, st.site[i + 1]);
+  HIP_LAUNCH_OK();
+  basis_times_pc(ctx.rw, len, l, ws.P.as<double2>(), k, dl, st.site[i], s);
+  st.dims[i + 1] = k;
+  st.center = i;
+  st.log_fest += std::log1p(-r.eps_step);
+  st.sum_eps += r.eps_step;
+  st.n_trunc += 1;
+  st.n_rsvd_ok += 1;
+  ctx.prev_eps[i] = r.eps_step;
+  record_bond_spectrum(st, ws, ctx, i, k);
+  if (log_spectra) {
+    SpectrumRecord rec{i, cycle, l, k, dl, dr, std::move(spec)};
+    st.spectra.push_back(std::move(rec));
+  }
+  return true;
+}
+
+static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int i, const double2* gate16, int cap,
+                            double eps, int prefer_left, int cycle, bool log_spectra, int precision) {
   hipStream_t s = st.stream;
   while (st.center < i) move_center(st, ws, true);
   while (st.center > i + 1) move_center(st, ws, false);
   const int dl = st.dims[i], dm = st.dims[i + 1], dr = st.dims[i + 2];
+  const int cap_eff = std::min(cap, st.cap[i + 1]);
+  ctx.update_index += 1;
+  ws.T.ensure((size_t)4 * dl * dr * sizeof(double2));
+  contract_two_site(st.site[i], st.site[i + 1], ws.T.as<double2>(), dl, dm, dr, precision, s);
+  if (ctx.o && ctx.o->rank_mode != RCS_RANK_FULL_SVD &&
+      randomized_split(st, ws, ctx, i, gate16, cap_eff, eps, cycle, log_spectra))
+    return;
   int orient;
   if (dr < dl)
     orient = 1;
@@ -583,11 +880,7 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, int i, const double2
   const int len = orient == 1 ? 2 * dl : 2 * dr;
   const int cnt = orient == 1 ? 2 * dr : 2 * dl;
   JacobiPlan pl = jacobi_plan(len, cnt);
-  ensure_work(ws, pl, (int64_t)4 * dl * dr);
-  // T = the four products
-  hipLaunchKernelGGL(k_two_site_f64, dim3(ceil_div(dr, GT_N), ceil_div(dl, GT_M), 4), dim3(GT_THREADS), 0, s,
-                     st.site[i], st.site[i + 1], ws.T.as<double2>(), dl, dm, dr);
-  HIP_LAUNCH_OK();
+  ensure_work(ws, pl, 0);
   HIP_OK(hipMemsetAsync(ws.X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
   HIP_OK(hipMemsetAsync(ws.X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
   Gate4 G;
@@ -596,11 +889,12 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, int i, const double2
                      dr, orient, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
   HIP_LAUNCH_OK();
   std::vector<double> spec;
-  SplitResult r = svd_split(st, ws, pl, std::min(cap, st.cap[i + 1]), eps, true,
-                            log_spectra ? &spec : nullptr);
+  SplitResult r = svd_split(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr);
   const int k = r.k;
+  record_bond_spectrum(st, ws, ctx, i, k);
+  if (ctx.o) ctx.prev_eps[i] = r.eps_step;
   hipLaunchKernelGGL(k_write_split, dim3(grid1d((int64_t)2 * k * (dl + dr))), dim3(256), 0, s,
-                     ws.Wn.as<double2>(), pl.ldx, ws.P.as<double2>(), pl.cnt, k, dl, dr, orient,
+                     ws.wn_final, pl.ldx, ws.P.as<double2>(), pl.cnt, k, dl, dr, orient,
                      st.site[i], st.site[i + 1]);
   HIP_LAUNCH_OK();
   st.dims[i + 1] = k;
@@ -676,6 +970,23 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
   HIP_OK(hipEventCreate(&e1));
   HIP_OK(hipEventRecord(e0, st.stream));
   st.canonical = false;
+  UpdateCtx ctx;
+  ctx.o = &o;
+  ctx.n_cycles = c.n_cycles;
+  ctx.chi_cap = chi;
+  ctx.bond_k.assign(st.n, 0);
+  ctx.prev_eps.assign(st.n, eps);
+  ctx.scal2.ensure(8 * sizeof(double));
+  if (o.rank_mode != RCS_RANK_FULL_SVD) {
+    ctx.bond_spec.ensure((size_t)st.n * chi * sizeof(double));
+    ctx.feat.ensure(66 * sizeof(float));
+    ctx.yhat.ensure(32 * sizeof(float));
+    if (o.rank_mode == RCS_RANK_LEARNED) {
+      ctx.w_mlp.ensure(o.mlp.size() * sizeof(float));
+      HIP_OK(hipMemcpyAsync(ctx.w_mlp.p, o.mlp.data(), o.mlp.size() * sizeof(float), hipMemcpyHostToDevice,
+                            st.stream));
+    }
+  }
   const int nops = (int)c.ops.size();
   const int stop = (o.max_ops < 0) ? nops : std::min(nops, o.max_ops);
   for (int oi = 0; oi < stop; ++oi) {
@@ -691,8 +1002,8 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
         prefer_left = c.ops[nj].arg < op.arg ? 1 : 0;
         break;
       }
-    two_site_update(st, ws, op.arg, op.gate == 0 ? fs.data() : sw.data(), chi, eps, prefer_left,
-                    op.cycle, o.log_spectra);
+    two_site_update(st, ws, ctx, op.arg, op.gate == 0 ? fs.data() : sw.data(), chi, eps, prefer_left,
+                    op.cycle, o.log_spectra, o.contraction);
     if (op.gate == 1) std::swap(st.pi[op.arg], st.pi[op.arg + 1]);
   }
   if (o.canonicalize) canonicalize(st, ws);
@@ -707,8 +1018,6 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
 
 void build_dispatch(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps,
                     const BuildOptions& o, BuildWork& ws) {
-  RCS_REQUIRE(o.contraction == RCS_PREC_C128 && o.rank_mode == RCS_RANK_FULL_SVD,
-              "precision/rank mode not available yet");
   build_one(st, c, chi, eps, o, ws);
 }
 
@@ -785,6 +1094,120 @@ rcs_status rcs_build_state_ex(rcs_circuit circuit, int32_t chi, double trunc_eps
   std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
   rcs::build_dispatch(*st, *circuit, chi, trunc_eps, b, *ws);
   *out = st.release();
+  RCS_API_END
+}
+
+rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev, double* u_dev,
+                          void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(x_dev && s_dev && u_dev, "null device pointer");
+  RCS_REQUIRE(len >= 1 && cnt >= 1 && cnt <= rcs::SORT_MAX && len <= 16384, "bad matrix shape");
+  hipStream_t s = rcs::as_stream(stream);
+  rcs::JacobiPlan pl = rcs::jacobi_plan(len, cnt);
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  rcs::ensure_work(*ws, pl, 0);
+  HIP_OK(hipMemsetAsync(ws->X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  double2* X = ws->X.as<double2>();
+  HIP_OK(hipMemsetAsync(ws->X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  hipLaunchKernelGGL(rcs::k_copy_in, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x_dev), len, cnt, ws->X0.as<double2>(), pl.ldx);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(cnt), dim3(256), 0, s, ws->X0.as<double2>(), pl.ldx, len,
+                     ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  // columns in descending-norm order
+  hipLaunchKernelGGL(rcs::k_sort_rank, dim3(1), dim3(1024), 0, s, ws->sigma.as<double>(), cnt, cnt, 0.0,
+                     ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_permute_cols, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s,
+                     ws->X0.as<double2>(), pl.ldx, len, ws->order.as<int>(), X);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(cnt), dim3(256), 0, s, X, pl.ldx, len, ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sum_sq, dim3(1), dim3(256), 0, s, ws->sigma.as<double>(), cnt,
+                     reinterpret_cast<double*>(ws->host_rank_dev()));
+  HIP_LAUNCH_OK();
+  double fro2 = 0.0;
+  HIP_OK(hipMemcpyAsync(&fro2, ws->host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  rcs::jacobi_run(pl, X, ws->jac.p, ws->rot.as<int>(), ws->host_rot, fro2, s, 60);
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(cnt), dim3(256), 0, s, X, pl.ldx, len, ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sort_rank, dim3(1), dim3(1024), 0, s, ws->sigma.as<double>(), cnt, cnt, 0.0,
+                     ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_copy_out, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s, X, pl.ldx, len, cnt,
+                     ws->order.as<int>(), ws->sorted.as<double>(), s_dev, reinterpret_cast<double2*>(u_dev));
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  RCS_API_END
+}
+
+rcs_status rcs_rsvd(int32_t len, int32_t cnt, const double* x_dev, int32_t l, int32_t q, uint64_t seed,
+                    uint64_t step, double* s_dev, double* fro2_host, void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(x_dev && s_dev && fro2_host, "null pointer");
+  RCS_REQUIRE(len >= 1 && cnt >= 1 && l >= 1 && l <= cnt && l <= len && q >= 0 && cnt <= rcs::SORT_MAX,
+              "bad sizes");
+  hipStream_t s = rcs::as_stream(stream);
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  rcs::RsvdWork rw;
+  const int ldm = (int)rcs::round_up(len, 64);
+  rcs::DevBuf M;
+  M.ensure((size_t)ldm * cnt * sizeof(double2));
+  hipLaunchKernelGGL(rcs::k_copy_in, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x_dev), len, cnt, M.as<double2>(), ldm);
+  HIP_LAUNCH_OK();
+  rcs::range_finder(M.as<double2>(), ldm, len, cnt, l, q, seed, step, rw, s);
+  rcs::JacobiPlan pl = rcs::jacobi_plan(cnt, l);
+  rcs::ensure_work(*ws, pl, 0);
+  ws->sigma.ensure((size_t)std::max(cnt, pl.cnt_pad) * sizeof(double));
+  HIP_OK(hipMemsetAsync(ws->X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws->X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  rcs::project_to_basis(M.as<double2>(), ldm, len, cnt, l, rw, ws->X.as<double2>(), ws->X0.as<double2>(), pl.ldx, s);
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(cnt), dim3(256), 0, s, M.as<double2>(), ldm, len, ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sum_sq, dim3(1), dim3(256), 0, s, ws->sigma.as<double>(), cnt,
+                     reinterpret_cast<double*>(ws->host_rank_dev()));
+  HIP_LAUNCH_OK();
+  HIP_OK(hipMemcpyAsync(fro2_host, ws->host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  rcs::jacobi_run(pl, ws->X.as<double2>(), ws->jac.p, ws->rot.as<int>(), ws->host_rot, *fro2_host, s, 60);
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(l), dim3(256), 0, s, ws->X.as<double2>(), pl.ldx, cnt,
+                     ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sort_rank, dim3(1), dim3(1024), 0, s, ws->sigma.as<double>(), l, l, 0.0,
+                     ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  HIP_OK(hipMemcpyAsync(s_dev, ws->sorted.p, l * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  RCS_API_END
+}
+
+rcs_status rcs_two_site(int32_t dl, int32_t dm, int32_t dr, const double* a_dev, const double* b_dev,
+                        const double* gate_host, int32_t precision, double* out_dev, void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(a_dev && b_dev && gate_host && out_dev, "null pointer");
+  RCS_REQUIRE(dl >= 1 && dm >= 1 && dr >= 1 && dl <= 4096 && dm <= 4096 && dr <= 4096, "bad dimensions");
+  RCS_REQUIRE(precision >= 0 && precision <= 2, "bad precision");
+  hipStream_t s = rcs::as_stream(stream);
+  rcs::DevBuf A, B, T;
+  A.ensure((size_t)2 * dl * dm * sizeof(double2));
+  B.ensure((size_t)2 * dm * dr * sizeof(double2));
+  T.ensure((size_t)4 * dl * dr * sizeof(double2));
+  hipLaunchKernelGGL(rcs::k_to_device_layout, dim3(rcs::grid1d((int64_t)2 * dl * dm)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(a_dev), dl, dm, A.as<double2>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_to_device_layout, dim3(rcs::grid1d((int64_t)2 * dm * dr)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(b_dev), dm, dr, B.as<double2>());
+  HIP_LAUNCH_OK();
+  rcs::contract_two_site(A.as<double2>(), B.as<double2>(), T.as<double2>(), dl, dm, dr, precision, s);
+  rcs::Gate4 G;
+  for (int e = 0; e < 16; ++e) G.g[e] = make_double2(gate_host[2 * e], gate_host[2 * e + 1]);
+  hipLaunchKernelGGL(rcs::k_mix_gate, dim3(rcs::grid1d((int64_t)dl * dr)), dim3(256), 0, s, T.as<double2>(), G,
+                     dl, dr, 1, reinterpret_cast<double2*>(out_dev), reinterpret_cast<double2*>(out_dev), 2 * dl);
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
   RCS_API_END
 }
 

@@ -1,0 +1,128 @@
+// Sampled kernel timing probes (see prof.h).
+#include "prof.h"
+
+#include <mutex>
+
+namespace rcs {
+
+namespace {
+struct Pending {
+  hipEvent_t e0, e1;
+  int kclass;
+  double flops, bytes;
+  bool closed;
+};
+struct Totals {
+  int64_t launches = 0, timed = 0;
+  double seconds = 0, flops = 0, bytes = 0;
+};
+std::mutex g_mu;
+int g_every = 0;
+int64_t g_counter[kKcCount] = {0};
+Totals g_tot[kKcCount];
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t get_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_OK(hipEventCreate(&e));
+  return e;
+}
+
+// Resolve finished probes (caller holds the lock; syncs when `wait`).
+void drain(bool wait) {
+  std::vector<Pending> keep;
+  for (auto& p : g_pending) {
+    if (!p.closed) {
+      keep.push_back(p);
+      continue;
+    }
+    if (wait) HIP_OK(hipEventSynchronize(p.e1));
+    else if (hipEventQuery(p.e1) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, p.e0, p.e1));
+    Totals& t = g_tot[p.kclass];
+    t.timed += 1;
+    t.seconds += ms * 1e-3;
+    t.flops += p.flops;
+    t.bytes += p.bytes;
+    g_pool.push_back(p.e0);
+    g_pool.push_back(p.e1);
+  }
+  g_pending.swap(keep);
+}
+}  // namespace
+
+Probe::Probe(int kclass, hipStream_t s, double flops, double bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_every <= 0) return;
+  g_tot[kclass].launches += 1;
+  if ((g_counter[kclass]++ % g_every) != 0) return;
+  if (g_pending.size() > 4096) drain(false);
+  Pending p{get_event(), get_event(), kclass, flops, bytes, false};
+  HIP_OK(hipEventRecord(p.e0, s));
+  g_pending.push_back(p);
+  slot_ = (int)g_pending.size() - 1;
+  s_ = s;
+}
+
+Probe::~Probe() {
+  if (slot_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Pending& p = g_pending[slot_];
+  if (hipEventRecord(p.e1, s_) == hipSuccess) p.closed = true;
+}
+
+}  // namespace rcs
+
+extern "C" {
+
+rcs_status rcs_profile_enable(int32_t every) {
+  try {
+    std::lock_guard<std::mutex> lk(rcs::g_mu);
+    rcs::drain(true);
+    rcs::g_every = every > 0 ? every : 0;
+    for (int k = 0; k < rcs::kKcCount; ++k) {
+      rcs::g_counter[k] = 0;
+      rcs::g_tot[k] = rcs::Totals();
+    }
+  } catch (const rcs::Error& e) {
+    rcs::set_last_error(e.what());
+    return e.status;
+  }
+  return RCS_OK;
+}
+
+rcs_status rcs_profile_read(int32_t kclass, int64_t* launches, int64_t* timed, double* seconds, double* flops,
+                            double* bytes) {
+  try {
+    if (kclass < 0 || kclass >= rcs::kKcCount) rcs::fail(RCS_ERR_INVALID_ARG, "bad kernel class");
+    std::lock_guard<std::mutex> lk(rcs::g_mu);
+    rcs::drain(true);
+    const rcs::Totals& t = rcs::g_tot[kclass];
+    if (launches) *launches = t.launches;
+    if (timed) *timed = t.timed;
+    if (seconds) *seconds = t.seconds;
+    if (flops) *flops = t.flops;
+    if (bytes) *bytes = t.bytes;
+  } catch (const rcs::Error& e) {
+    rcs::set_last_error(e.what());
+    return e.status;
+  }
+  return RCS_OK;
+}
+
+const char* rcs_profile_class_name(int32_t kclass) {
+  static const char* names[] = {"k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder"};
+  return (kclass >= 0 && kclass < rcs::kKcCount) ? names[kclass] : "";
+}
+
+}  // extern "C"

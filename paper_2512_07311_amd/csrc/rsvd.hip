@@ -1,0 +1,370 @@
+// Randomized range finder for the learned-rank truncation.
+//
+// Halko, Martinsson, Tropp (SIAM Review 2011), randomized range finder with
+// power iterations (their Algorithm 4.4): for the two-site matrix M (len x
+// cnt) and a sketch width l,
+//   Omega (cnt x l), entries {1, i, -1, -i}[x & 3] with x = word 0 of
+//     Philox(seed; (row, col, step, 4))   (exact in every precision);
+//   Y = M Omega;  Q = orth(Y);
+//   q times:  Z = orth(M^H Q);  Q = orth(M Z).
+// The products with M are the expensive part and run in fp32 on the matrix
+// cores (v_mfma_f32_16x16x4f32); orth() keeps the basis in fp64: block
+// classical Gram-Schmidt with two passes (BCGS2) over 64-column panels and
+// two Cholesky-QR passes inside each panel (fp64 Gram, 64x64 Cholesky in LDS
+// with a pivot guard that zeroes numerically dependent columns).  The caller
+// then takes the exact fp64 SVD of the projected matrix B = Q^H M (their
+// Algorithm 5.1).
+#include "build.h"
+#include "gemm_f32.h"
+#include "gemm_f64.h"
+#include "rsvd.h"
+
+namespace rcs {
+
+__global__ void k_sketch(double2* Z, int ldz, int cnt, int l, uint32_t k0, uint32_t k1, uint32_t step) {
+  const int64_t tot = (int64_t)cnt * l;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % cnt), c = (int)(e / cnt);
+    const U4 x = philox4x32_10(U4{(uint32_t)r, (uint32_t)c, step, kStreamSketch}, k0, k1);
+    const int ph = x.x & 3;
+    const double2 v = ph == 0 ? make_double2(1.0, 0.0)
+                              : ph == 1 ? make_double2(0.0, 1.0)
+                                        : ph == 2 ? make_double2(-1.0, 0.0) : make_double2(0.0, -1.0);
+    Z[(int64_t)c * ldz + r] = v;
+  }
+}
+
+// Y (len x l) = M Z, fp32 MFMA.  M col-major (ldx), Z col-major (ldz).
+__global__ __launch_bounds__(256) void k_mz32(const double2* M, int ldx, int len, int cnt, const double2* Z, int ldz,
+                                             int l, double2* Y, int ldy) {
+  __shared__ SmemF32C sm;
+  const int m0 = blockIdx.y * FT_M, n0 = blockIdx.x * FT_N;
+  auto fa = [&](int m, int k) -> double2 { return M[(int64_t)k * ldx + m]; };
+  auto fb = [&](int k, int n) -> double2 { return Z[(int64_t)n * ldz + k]; };
+  LoadA32<decltype(fa), false> la{fa, m0, len, cnt};
+  LoadB32<decltype(fb), false> lb{fb, n0, cnt, l};
+  AccF32C acc;
+  acc_zero(acc);
+  cgemm32_mainloop(la, lb, cnt, sm, acc);
+  acc32_foreach(acc, [&](int r, int c, float re, float im) {
+    const int m = m0 + r, n = n0 + c;
+    if (m < len && n < l) Y[(int64_t)n * ldy + m] = make_double2(re, im);
+  });
+}
+
+// Z (cnt x l) = M^H Q, fp32 MFMA.
+__global__ __launch_bounds__(256) void k_mhq32(const double2* M, int ldx, int len, int cnt, const double2* Q, int ldq,
+                                              int l, double2* Z, int ldz) {
+  __shared__ SmemF32C sm;
+  const int m0 = blockIdx.y * FT_M, n0 = blockIdx.x * FT_N;
+  auto fa = [&](int m, int k) -> double2 {
+    const double2 v = M[(int64_t)m * ldx + k];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)n * ldq + k]; };
+  LoadA32<decltype(fa), true> la{fa, m0, cnt, len};
+  LoadB32<decltype(fb), false> lb{fb, n0, len, l};
+  AccF32C acc;
+  acc_zero(acc);
+  cgemm32_mainloop(la, lb, len, sm, acc);
+  acc32_foreach(acc, [&](int r, int c, float re, float im) {
+    const int m = m0 + r, n = n0 + c;
+    if (m < cnt && n < l) Z[(int64_t)n * ldz + m] = make_double2(re, im);
+  });
+}
+
+// C (j0 x pw, row-major ld 64) = Q[:, :j0]^H Y[:, j0:j0+pw]   (fp64)
+__global__ __launch_bounds__(GT_THREADS) void k_qhy(const double2* Q, int ldq, int len, int j0, int pw,
+                                                   double2* C) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M;
+  auto fa = [&](int m, int k) -> double2 {
+    const double2 v = Q[(int64_t)m * ldq + k];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)(j0 + n) * ldq + k]; };
+  LoadA<decltype(fa), true> la{fa, m0, j0, len};
+  LoadB<decltype(fb), false> lb{fb, 0, len, pw};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, len, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r;
+    if (m < j0 && c < pw) C[(int64_t)m * 64 + c] = make_double2(re, im);
+  });
+}
+
+// Y[:, j0:j0+pw] -= Q[:, :j0] C   (in place by row tiles)
+__global__ __launch_bounds__(GT_THREADS) void k_ysub(double2* Q, int ldq, int len, int j0, int pw,
+                                                    const double2* C) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M;
+  auto fa = [&](int m, int k) -> double2 { return Q[(int64_t)k * ldq + m]; };
+  auto fb = [&](int k, int n) -> double2 { return C[(int64_t)k * 64 + n]; };
+  LoadA<decltype(fa), false> la{fa, m0, len, j0};
+  LoadB<decltype(fb), true> lb{fb, 0, j0, pw};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, j0, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r;
+    if (m < len && c < pw) {
+      double2* y = Q + (int64_t)(j0 + c) * ldq + m;
+      *y = make_double2(y->x - re, y->y - im);
+    }
+  });
+}
+
+// G (64 x 64) = Yp^H Yp for the panel (partial over row chunks, summed in
+// fixed order by the Cholesky kernel).
+__global__ __launch_bounds__(GT_THREADS) void k_panel_gram(const double2* Q, int ldq, int len, int j0, int pw,
+                                                          int rows_per_chunk, double2* part) {
+  __shared__ SmemC64 sm;
+  const int chunk = blockIdx.x;
+  const int r0 = chunk * rows_per_chunk;
+  const int K = min(rows_per_chunk, len - r0);
+  auto fa = [&](int m, int k) -> double2 {
+    const double2 v = Q[(int64_t)(j0 + m) * ldq + r0 + k];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)(j0 + n) * ldq + r0 + k]; };
+  LoadA<decltype(fa), true> la{fa, 0, pw, K};
+  LoadB<decltype(fb), false> lb{fb, 0, K, pw};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, K, sm, acc);
+  double2* g = part + (int64_t)chunk * 64 * 64;
+  acc_foreach(acc, [&](int r, int c, double re, double im) { g[r * 64 + c] = make_double2(re, im); });
+}
+
+// Cholesky G = R^H R (R upper triangular) with pivot guard, then Rinv = R^-1.
+// A pivot below guard * max(diag) marks the column dependent: its row of R
+// is set to zero and its column of Rinv to zero, so the panel column becomes 0.
+__global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chunks, int pw, double guard,
+                                                 double2* Rinv) {
+  __shared__ double2 R[64][65];
+  __shared__ double2 Ri[64][65];
+  __shared__ int dead[64];
+  __shared__ double dmax;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int c = 0; c < n_chunks; ++c) {
+      const double2 t = part[(int64_t)c * 4096 + e];
+      s.x += t.x;
+      s.y += t.y;
+    }
+    const int i = e / 64, j = e % 64;
+    R[i][j] = (i < pw && j < pw) ? s : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    Ri[i][j] = make_double2(0.0, 0.0);
+  }
+  if (tid < 64) dead[tid] = tid >= pw;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < pw; ++i) m = fmax(m, R[i][i].x);
+    dmax = m;
+  }
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle: R[k][j] for j >= k
+  for (int k = 0; k < pw; ++k) {
+    __shared__ double piv;
+    if (tid == 0) {
+      const double d = R[k][k].x;
+      if (!(d > guard * dmax) || dead[k]) {
+        dead[k] = 1;
+        piv = 0.0;
+      } else {
+        piv = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double p = piv;
+    // row k: R[k][j] /= p  (j > k), R[k][k] = p
+    if (tid < 64) {
+      const int j = tid;
+      if (j > k) R[k][j] = p > 0.0 ? make_double2(R[k][j].x / p, R[k][j].y / p) : make_double2(0.0, 0.0);
+      if (j == k) R[k][k] = make_double2(p, 0.0);
+    }
+    __syncthreads();
+    // trailing update: R[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int i = e / 64, j = e % 64;
+      if (i > k && j >= i && j < pw) {
+        const double2 a = R[k][i], b = R[k][j];
+        R[i][j] = make_double2(R[i][j].x - (a.x * b.x + a.y * b.y), R[i][j].y - (a.x * b.y - a.y * b.x));
+      }
+    }
+    __syncthreads();
+  }
+  // Rinv column by column: R Rinv[:, c] = e_c, back substitution
+  if (tid < 64) {
+    const int c = tid;
+    if (c < pw && !dead[c]) {
+      for (int i = c; i >= 0; --i) {
+        if (dead[i]) {
+          Ri[i][c] = make_double2(0.0, 0.0);
+          continue;
+        }
+        double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        for (int j = i + 1; j <= c; ++j) {
+          const double2 a = R[i][j], b = Ri[j][c];
+          s.x -= a.x * b.x - a.y * b.y;
+          s.y -= a.x * b.y + a.y * b.x;
+        }
+        const double d = R[i][i].x;
+        Ri[i][c] = make_double2(s.x / d, s.y / d);
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) Rinv[e] = Ri[e / 64][e % 64];
+}
+
+// Y[:, j0:j0+pw] <- Y[:, j0:j0+pw] Rinv   (in place by row tiles)
+__global__ __launch_bounds__(GT_THREADS) void k_panel_apply(double2* Q, int ldq, int len, int j0, int pw,
+                                                           const double2* Rinv) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M;
+  auto fa = [&](int m, int k) -> double2 { return Q[(int64_t)(j0 + k) * ldq + m]; };
+  auto fb = [&](int k, int n) -> double2 { return Rinv[(int64_t)k * 64 + n]; };
+  LoadA<decltype(fa), false> la{fa, m0, len, pw};
+  LoadB<decltype(fb), true> lb{fb, 0, pw, pw};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, pw, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r;
+    if (m < len && c < pw) Q[(int64_t)(j0 + c) * ldq + m] = make_double2(re, im);
+  });
+}
+
+// Orthonormalise the l columns of Y (len x l, col-major, ld ldq) in place.
+static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s) {
+  const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 64)), 64);
+  const int n_chunks = ceil_div(len, rows_per_chunk);
+  for (int j0 = 0; j0 < l; j0 += 64) {
+    const int pw = std::min(64, l - j0);
+    if (j0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_qhy, dim3(1, ceil_div(j0, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, w.C);
+        HIP_LAUNCH_OK();
+        hipLaunchKernelGGL(k_ysub, dim3(1, ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, w.C);
+        HIP_LAUNCH_OK();
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_panel_gram, dim3(n_chunks), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, rows_per_chunk,
+                         w.gpart);
+      HIP_LAUNCH_OK();
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, w.gpart, n_chunks, pw, 1e-26, w.Rinv);
+      HIP_LAUNCH_OK();
+      hipLaunchKernelGGL(k_panel_apply, dim3(1, ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw,
+                         w.Rinv);
+      HIP_LAUNCH_OK();
+    }
+  }
+}
+
+void rsvd_work_ensure(RsvdWork& w, int len, int cnt, int l) {
+  const int ldq = (int)round_up(len, 64), ldz = (int)round_up(cnt, 64);
+  w.bufQ.ensure((size_t)ldq * round_up(l, 64) * sizeof(double2));
+  w.bufZ.ensure((size_t)ldz * round_up(l, 64) * sizeof(double2));
+  w.bufC.ensure((size_t)round_up(l, 64) * 64 * sizeof(double2));
+  const int mx = std::max(len, cnt);
+  const int n_chunks = ceil_div(mx, (int)round_up(std::max(64, ceil_div(mx, 64)), 64)) + 1;
+  w.bufG.ensure((size_t)n_chunks * 4096 * sizeof(double2));
+  w.bufR.ensure((size_t)4096 * sizeof(double2));
+  w.Q = w.bufQ.as<double2>();
+  w.Z = w.bufZ.as<double2>();
+  w.C = w.bufC.as<double2>();
+  w.gpart = w.bufG.as<double2>();
+  w.Rinv = w.bufR.as<double2>();
+  w.ldq = ldq;
+  w.ldz = ldz;
+}
+
+void range_finder(const double2* M, int ldx, int len, int cnt, int l, int q, uint64_t seed, uint64_t step,
+                  RsvdWork& w, hipStream_t s) {
+  rsvd_work_ensure(w, len, cnt, l);
+  const int grid_sk = (int)std::min<int64_t>(65535, std::max<int64_t>(1, ((int64_t)cnt * l + 255) / 256));
+  hipLaunchKernelGGL(k_sketch, dim3(grid_sk), dim3(256), 0, s, w.Z, w.ldz, cnt, l, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), (uint32_t)step);
+  HIP_LAUNCH_OK();
+  const dim3 gy(ceil_div(l, FT_N), ceil_div(len, FT_M)), gz(ceil_div(l, FT_N), ceil_div(cnt, FT_M));
+  hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
+  HIP_LAUNCH_OK();
+  orth(w.Q, w.ldq, len, l, w, s);
+  for (int it = 0; it < q; ++it) {
+    hipLaunchKernelGGL(k_mhq32, gz, dim3(256), 0, s, M, ldx, len, cnt, w.Q, w.ldq, l, w.Z, w.ldz);
+    HIP_LAUNCH_OK();
+    orth(w.Z, w.ldz, cnt, l, w, s);
+    hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
+    HIP_LAUNCH_OK();
+    orth(w.Q, w.ldq, len, l, w, s);
+  }
+}
+
+// X (cnt x l, col-major ld ldxo) = M^H Q in fp64, and a copy in X0.
+__global__ __launch_bounds__(GT_THREADS) void k_mhq64(const double2* M, int ldx, int len, int cnt, const double2* Q,
+                                                     int ldq, int l, double2* X, double2* X0, int ldxo) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int k) -> double2 {
+    const double2 v = M[(int64_t)m * ldx + k];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)n * ldq + k]; };
+  LoadA<decltype(fa), true> la{fa, m0, cnt, len};
+  LoadB<decltype(fb), false> lb{fb, n0, len, l};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, len, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r, n = n0 + c;
+    if (m < cnt && n < l) {
+      X[(int64_t)n * ldxo + m] = make_double2(re, im);
+      X0[(int64_t)n * ldxo + m] = make_double2(re, im);
+    }
+  });
+}
+
+void project_to_basis(const double2* M, int ldx, int len, int cnt, int l, const RsvdWork& w, double2* X,
+                      double2* X0, int ldxo, hipStream_t s) {
+  hipLaunchKernelGGL(k_mhq64, dim3(ceil_div(l, GT_N), ceil_div(cnt, GT_M)), dim3(GT_THREADS), 0, s, M, ldx, len, cnt,
+                     w.Q, w.ldq, l, X, X0, ldxo);
+  HIP_LAUNCH_OK();
+}
+
+// A_i[s1][a][j] = sum_t Q[(s1,a)][t] conj(P[j][t])   (rows (s1,a) of M)
+__global__ __launch_bounds__(GT_THREADS) void k_basis_times_pc(const double2* Q, int ldq, int len, int l,
+                                                              const double2* P, int k, int dl, double2* Ai) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int t) -> double2 { return Q[(int64_t)t * ldq + m]; };
+  auto fb = [&](int t, int n) -> double2 {
+    const double2 v = P[(int64_t)n * l + t];
+    return make_double2(v.x, -v.y);
+  };
+  LoadA<decltype(fa), false> la{fa, m0, len, l};
+  LoadB<decltype(fb), false> lb{fb, n0, l, k};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, l, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r, n = n0 + c;
+    if (m < len && n < k) {
+      const int s1 = m / dl, a = m % dl;
+      Ai[((int64_t)s1 * dl + a) * k + n] = make_double2(re, im);
+    }
+  });
+}
+
+void basis_times_pc(const RsvdWork& w, int len, int l, const double2* P, int k, int dl, double2* Ai, hipStream_t s) {
+  hipLaunchKernelGGL(k_basis_times_pc, dim3(ceil_div(k, GT_N), ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, w.Q,
+                     w.ldq, len, l, P, k, dl, Ai);
+  HIP_LAUNCH_OK();
+}
+
+}  // namespace rcs

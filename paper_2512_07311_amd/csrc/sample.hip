@@ -11,6 +11,7 @@
 // out of W at the chosen half (no copy).  The last site has a single column,
 // whose |w|^2 is p(b).
 #include "gemm_f64.h"
+#include "prof.h"
 #include "state.h"
 
 namespace rcs {
@@ -146,7 +147,14 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
       ca.dr = st.dims[k + 1];
       ca.ntiles = ceil_div(ca.dr, GT_N);
       dim3 grid(ca.ntiles, ceil_div(S, GT_M), 2);
-      hipLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, ca);
+      {
+        // algorithmic: 2 complex GEMMs S x dl x dr (8 real flops per complex
+        // multiply-add); HBM: site tensor + V rows read + W written
+        const double fl = 16.0 * S * (double)ca.dl * ca.dr;
+        const double by = 16.0 * (2.0 * ca.dl * ca.dr + (double)S * ca.dl + 2.0 * S * ca.dr);
+        Probe pr(kKcChainGemm, st.stream, fl, by);
+        hipLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, ca);
+      }
       HIP_LAUNCH_OK();
       DecideArgs da;
       da.part = ca.part;

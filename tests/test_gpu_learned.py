@@ -1,0 +1,157 @@
+"""GPU parity of the learned-rank pieces through the C-ABI: spectrum
+features, network forward / gradients / Adam against the fp64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from tests import inputs
+from tests.gpu_util import get_rcs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    return get_rcs()
+
+
+def test_spectrum_features(env):
+    rcs, torch = env
+    g = inputs.rng(3)
+    for k in [0, 1, 7, 300, 1024]:
+        s = np.sort(np.abs(g.standard_normal(k)) * 10.0 ** g.uniform(-9, 0, k))[::-1].copy()
+        sd = torch.from_numpy(s).cuda()
+        feat = torch.zeros(66, dtype=torch.float32, device="cuda")
+        rcs.spectrum_features(sd, k, 17, 53, 5, 14, feat)
+        torch.cuda.synchronize()
+        ref = mlp.features(s if k else None, 17, 53, 5, 14)
+        assert np.abs(feat.cpu().numpy() - ref).max() < 1e-6
+
+
+def test_forward_backward_adam(env):
+    rcs, torch = env
+    flat = inputs.mlp_init(7).astype(np.float32)
+    g = inputs.rng(8)
+    B = 256 + 3
+    x = g.standard_normal((B, 66)).astype(np.float32)
+    y = g.standard_normal((B, 32)).astype(np.float32)
+    w = torch.from_numpy(flat).cuda()
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    out = torch.zeros(B, 32, dtype=torch.float32, device="cuda")
+    rcs.mlp_forward(w, xd, out)
+    p = mlp.unpack(flat.astype(np.float64))
+    ref_out, _ = mlp.forward(p, x.astype(np.float64))
+    assert np.linalg.norm(out.cpu().numpy() - ref_out) / np.linalg.norm(ref_out) < 1e-5
+    grad = torch.zeros(mlp.n_params(), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rcs.mlp_backward(w, xd, yd, grad, loss)
+    ref_g = mlp.pack(mlp.backward(p, x.astype(np.float64), y.astype(np.float64)))
+    gg = grad.cpu().numpy()
+    assert np.linalg.norm(gg - ref_g) / np.linalg.norm(ref_g) < 1e-4
+    assert abs(loss.item() - mlp.loss(p, x.astype(np.float64), y.astype(np.float64))) < 1e-4
+    # Adam: two steps against the oracle's update on the same gradients
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    fm, fv = np.zeros(len(flat)), np.zeros(len(flat))
+    fw = flat.astype(np.float64)
+    for step in (1, 2):
+        rcs.mlp_adam(w, grad, m, v, step)
+        fw, fm, fv = mlp.adam_step(fw, gg.astype(np.float64), fm, fv, step)
+    torch.cuda.synchronize()
+    assert np.abs(w.cpu().numpy() - fw).max() < 1e-6
+
+
+def test_spectrum_targets(env):
+    rcs, torch = env
+    g = inputs.rng(4)
+    for m in [1, 5, 31, 64, 700]:
+        s = np.sort(np.abs(g.standard_normal(m)) * 10.0 ** g.uniform(-14, 0, m))[::-1].copy()
+        if m > 3:
+            s[-2:] = [1e-13, 0.0]
+        y = torch.zeros(32, dtype=torch.float32, device="cuda")
+        rcs.spectrum_targets(torch.from_numpy(s).cuda(), m, y)
+        torch.cuda.synchronize()
+        assert np.abs(y.cpu().numpy() - mlp.targets(s)).max() < 1e-5
+
+
+@pytest.mark.parametrize("ln,cnt,l,q,kind", [(96, 80, 20, 1, "decay"), (200, 256, 48, 2, "decay"),
+                                             (128, 128, 40, 2, "rank30")])
+def test_rsvd_matches_oracle(env, ln, cnt, l, q, kind):
+    """Randomized SVD with the same sketch as the oracle (Philox stream 4):
+    the singular values of Q^H M agree to the fp32 accuracy of the range
+    finder; exactly when the sketch covers the rank."""
+    from oracle import rsvd as orsvd
+    rcs, torch = env
+    if kind == "decay":
+        M = inputs.planted_matrix(ln, cnt, 0.8 ** np.arange(min(ln, cnt)), seed=5)
+    else:
+        M = inputs.planted_matrix(ln, cnt, np.linspace(2, 1, 30), seed=6)
+    x = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
+    s = torch.zeros(l, dtype=torch.float64, device="cuda")
+    fro2 = rcs.rsvd(x, l, q, 77, 3, s)
+    _, s_ref, _ = orsvd.rsvd(M, l, q, 77, 3)
+    got = s.cpu().numpy()
+    assert abs(fro2 - np.sum(np.abs(M) ** 2)) < 1e-12 * fro2
+    if kind == "rank30":
+        assert np.abs(got[:30] - s_ref[:30]).max() < 1e-12
+    else:
+        assert np.abs(got - s_ref).max() < 2e-5 * s_ref[0]
+    s_full = np.linalg.svd(M, compute_uv=False)
+    assert np.all(got <= s_full[:l] * (1 + 1e-12) + 1e-14)        # interlacing
+
+
+def test_learned_build_forced_fallback_equals_plain(env):
+    """tau < 0 rejects every randomized split: the learned build must then be
+    bitwise the plain fp64 build."""
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 10, 31)
+    w = inputs.mlp_init(1).astype(np.float32)
+    plain = rcs.State.build(c, 16, 1e-10)
+    learned = rcs.State.build(c, 16, 1e-10, rank_mode=1, mlp_weights=w, fallback_tau=-1.0)
+    a, b = plain.to_host(), learned.to_host()
+    assert all(np.array_equal(x, y) for x, y in zip(a[2], b[2]))
+    inf = learned.info()
+    assert inf.n_rsvd_accepted == 0 and inf.n_fallbacks > 0
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_randomized_build_accuracy(env, mode):
+    """Accepted randomized splits keep the state within the judge's budget:
+    amplitudes vs the fp64 oracle within sqrt of the extra discarded weight,
+    and F_est within 1% of the plain build's."""
+    from oracle import circuit as oc, mps
+    from paper_2512_07311_amd import learn
+    rcs, torch = env
+    c = rcs.Circuit(4, 6, 12, 41)
+    plain = rcs.State.build(c, 24, 1e-9, log_spectra=True)
+    w = None
+    if mode == 1:
+        X, Y = learn.dataset(plain.spectra(), c.n, 12, torch)
+        w, _ = learn.train(X, Y, torch, steps=300, batch=128, seed=3)
+    g = rcs.State.build(c, 24, 1e-9, rank_mode=mode, mlp_weights=w, fallback_tau=1e-6)
+    inf, pinf = g.info(), plain.info()
+    assert inf.canonical == 1
+    assert inf.n_rsvd_accepted + inf.n_fallbacks > 0
+    assert abs(np.exp(inf.log_fidelity_est) / np.exp(pinf.log_fidelity_est) - 1) < 0.01
+    om = mps.build(oc.Circuit(4, 6, 12, 41), 24, 1e-9)
+    b = inputs.random_bitstrings(c.n, 500, seed=2)
+    bits = torch.from_numpy(b.astype(np.int64)).cuda()
+    amps = torch.zeros(len(b), 2, dtype=torch.float64, device="cuda")
+    g.amplitudes(bits, amps)
+    a = amps.cpu().numpy()
+    got = a[:, 0] + 1j * a[:, 1]
+    ref = om.amplitudes(b)
+    extra = max(0.0, inf.sum_eps - pinf.sum_eps) + 1e-6 * max(inf.n_rsvd_accepted, 1)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 2 * np.sqrt(extra) + 1e-8
+
+
+def test_training_reduces_loss(env):
+    from paper_2512_07311_amd import learn
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 10, 51)
+    st = rcs.State.build(c, 16, 1e-10, log_spectra=True)
+    recs = st.spectra()
+    assert len(recs) == c.n_updates
+    X, Y = learn.dataset(recs, c.n, 10, torch)
+    w, losses = learn.train(X, Y, torch, steps=400, batch=64, seed=2, log_every=100)
+    assert losses[-1][1] < 0.5 * losses[0][1]
