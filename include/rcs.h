@@ -154,7 +154,11 @@ rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, 
                             uint64_t* bits_dev, double* log2p_dev);
 
 /* Shots from n states in one launch sequence: shot j of state i goes to
- * bits_dev[i * n_shots + j] (and log2p_dev likewise, nullable). */
+ * bits_dev[i * n_shots + j] (and log2p_dev likewise, nullable); identical to
+ * rcs_sample on each state.  Per site index one grouped GEMM launch covers
+ * every state that has that site; the whole sequence is captured into one
+ * HIP graph on a private stream and replayed (synchronous; orders after
+ * work already submitted to the first state's stream). */
 rcs_status rcs_sample_batch(const rcs_state* states, int32_t n, uint64_t n_shots, uint64_t seed,
                             uint64_t* bits_dev, double* log2p_dev);
 
@@ -284,6 +288,16 @@ rcs_status rcs_profile_enable(int32_t every);
 rcs_status rcs_profile_read(int32_t kclass, int64_t* launches, int64_t* timed, double* seconds,
                             double* flops, double* bytes);
 const char* rcs_profile_class_name(int32_t kclass);
+
+/* --------------------------------------------------------------- tuning
+ * Launch parameters of the fp64 Jacobi SVD per column-count bucket: the
+ * first entry with cnt <= cnt_max applies (block = 16 or 32 columns per
+ * block, inner_sweeps in [1, 8] two-sided sweeps per block-pair meeting).
+ * Process-wide; written by the autotuner (paper_2512_07311_amd/autotune.py)
+ * from device timings.  Without entries: block 32 for cnt >= 512, else 16;
+ * one inner sweep. */
+rcs_status rcs_tuning_set(int32_t cnt_max, int32_t block, int32_t inner_sweeps);
+void rcs_tuning_clear(void);
 
 /* ---------------------------------------------------------------- misc */
 const char* rcs_last_error(void);

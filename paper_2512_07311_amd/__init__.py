@@ -89,6 +89,7 @@ _SIGS = {
     "rcs_mlp_forward": [_vp, _vp, _i32, _vp, _vp],
     "rcs_mlp_backward": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "rcs_profile_enable": [_i32],
+    "rcs_tuning_set": [_i32, _i32, _i32],
     "rcs_profile_read": [_i32, _P(_i64), _P(_i64), _P(_d), _P(_d), _P(_d)],
     "rcs_mlp_adam": [_vp, _vp, _vp, _vp, _i32, _i32, C.c_float, C.c_float, C.c_float,
                      C.c_float, _vp],
@@ -99,6 +100,8 @@ for _name, _args in _SIGS.items():
     _f.restype = C.c_int
 _lib.rcs_last_error.restype = C.c_char_p
 _lib.rcs_version.restype = C.c_char_p
+_lib.rcs_tuning_clear.argtypes = []
+_lib.rcs_tuning_clear.restype = None
 _lib.rcs_profile_class_name.argtypes = [_i32]
 _lib.rcs_profile_class_name.restype = C.c_char_p
 _lib.rcs_circuit_destroy.argtypes = [_vp]
@@ -110,7 +113,7 @@ _lib.rcs_build_opts_default.restype = None
 
 EXPORTED = sorted(list(_SIGS) + ["rcs_last_error", "rcs_version", "rcs_circuit_destroy",
                                  "rcs_state_destroy", "rcs_build_opts_default",
-                                 "rcs_profile_class_name"])
+                                 "rcs_profile_class_name", "rcs_tuning_clear"])
 KERNEL_CLASSES = ["k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder"]
 
 
@@ -385,3 +388,11 @@ def profile_read(kclass):
                                  C.byref(by)))
     return dict(name=_lib.rcs_profile_class_name(int(kclass)).decode(), launches=a.value,
                 timed=b.value, seconds=sec.value, flops=fl.value, bytes=by.value)
+
+
+def tuning_set(cnt_max, block, inner_sweeps):
+    _check(_lib.rcs_tuning_set(int(cnt_max), int(block), int(inner_sweeps)))
+
+
+def tuning_clear():
+    _lib.rcs_tuning_clear()

@@ -255,9 +255,8 @@ rcs_status rcs_sample_batch(const rcs_state* states, int32_t n, uint64_t n_shots
     RCS_REQUIRE(states[i], "null state in batch");
     if (!states[i]->canonical) rcs::fail(RCS_ERR_STATE, "state in batch is not right-canonical");
   }
-  for (int i = 0; i < n; ++i)
-    rcs::run_chain(*states[i], 0, n_shots, seed, 0, bits_dev + (uint64_t)i * n_shots,
-                   log2p_dev ? log2p_dev + (uint64_t)i * n_shots : nullptr, nullptr, nullptr);
+  std::vector<rcs_state_s*> v(states, states + n);
+  rcs::run_chain_batch(v.data(), n, n_shots, seed, bits_dev, log2p_dev, n ? states[0]->stream : nullptr);
   RCS_API_END
 }
 

@@ -21,7 +21,10 @@
 // A pair whose two blocks were not rotated since the pair last met is
 // skipped (it is still orthogonal), so late sweeps cost almost nothing.  A
 // sweep that rotates nothing ends the iteration.
+#include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "gemm_f64.h"
 #include "jacobi.h"
@@ -326,15 +329,58 @@ static bool debug_jacobi() {
   return v == 1;
 }
 
-int jacobi_default_block(int cnt) {
-  const char* e = std::getenv("RCS_JACOBI_BLOCK");
-  if (e && (std::atoi(e) == 16 || std::atoi(e) == 32)) return std::atoi(e);
-  return cnt >= 512 ? 32 : 16;
+// Tuning table: buckets (cnt_max ascending) -> block width, inner sweeps.
+namespace {
+struct TuneEntry {
+  int cnt_max, jb, inner;
+};
+std::vector<TuneEntry> g_tune;
+std::mutex g_tune_mu;
+}  // namespace
+
+void tuning_set(int cnt_max, int jb, int inner) {
+  RCS_REQUIRE(jb == 16 || jb == 32, "block width must be 16 or 32");
+  RCS_REQUIRE(inner >= 1 && inner <= 8, "inner sweeps must be in [1, 8]");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.cnt_max == cnt_max) {
+      e.jb = jb;
+      e.inner = inner;
+      return;
+    }
+  g_tune.push_back({cnt_max, jb, inner});
+  std::sort(g_tune.begin(), g_tune.end(), [](const TuneEntry& a, const TuneEntry& b) { return a.cnt_max < b.cnt_max; });
+}
+
+void tuning_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+static void tuned(int cnt, int* jb, int* inner) {
+  *jb = cnt >= 512 ? 32 : 16;
+  *inner = 1;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune)
+      if (cnt <= e.cnt_max) {
+        *jb = e.jb;
+        *inner = e.inner;
+        break;
+      }
+  }
+  const char* b = std::getenv("RCS_JACOBI_BLOCK");
+  if (b && (std::atoi(b) == 16 || std::atoi(b) == 32)) *jb = std::atoi(b);
+  const char* i = std::getenv("RCS_JACOBI_INNER");
+  if (i && std::atoi(i) >= 1 && std::atoi(i) <= 8) *inner = std::atoi(i);
 }
 
 JacobiPlan jacobi_plan(int len, int cnt, int jb) {
   JacobiPlan pl;
-  if (jb <= 0) jb = jacobi_default_block(cnt);
+  int tjb, tin;
+  tuned(cnt, &tjb, &tin);
+  if (jb <= 0) jb = tjb;
+  pl.inner = tin;
   RCS_REQUIRE(jb == 16 || jb == 32, "Jacobi block must be 16 or 32 columns");
   pl.jb = jb;
   pl.len = len;
@@ -358,6 +404,84 @@ size_t jacobi_work_bytes(const JacobiPlan& pl) {
          256;
 }
 
+static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bool first) {
+  hipLaunchKernelGGL(k_jac_roll, dim3(1), dim3(256), 0, stream, a.rot_prev, a.rot_cur, a.rot_count, pl.nbp,
+                     first ? 1 : 0);
+  HIP_LAUNCH_OK();
+  for (int r = 0; r < pl.nbp - 1; ++r) {
+    a.round = r;
+    // nominal algorithmic work of a round with every pair active: Gram and
+    // update are each n_pairs complex GEMMs of len x JP x JP
+    const double JPd = 2.0 * pl.jb;
+    const double fl = 8.0 * pl.len * JPd * JPd * pl.n_pairs;
+    const double by = 16.0 * (double)pl.len * JPd * pl.n_pairs;
+    {
+      Probe pr(kKcJacGram, stream, fl, by);
+      if (pl.jb == 16)
+        hipLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+      else
+        hipLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+    }
+    HIP_LAUNCH_OK();
+    {
+      Probe pr(kKcJacRotate, stream, fl, 2.0 * by);
+      if (pl.jb == 16)
+        hipLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+      else
+        hipLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+    }
+    HIP_LAUNCH_OK();
+  }
+}
+
+static bool use_graphs() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("RCS_JACOBI_GRAPH");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+// Cached executable graphs of one sweep (not the first), keyed by the plan
+// and the buffers they were captured with.
+namespace {
+struct SweepGraph {
+  int len, cnt, jb, inner;
+  void *x, *work;
+  int* rc;
+  hipGraphExec_t exec;
+};
+std::vector<SweepGraph> g_graphs;
+std::mutex g_graph_mu;
+}  // namespace
+
+static hipGraphExec_t sweep_graph(const JacobiPlan& pl, const JacArgs& a, void* work, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto& g : g_graphs)
+    if (g.len == pl.len && g.cnt == pl.cnt && g.jb == pl.jb && g.inner == a.max_inner && g.x == a.x &&
+        g.work == work && g.rc == a.rot_count)
+      return g.exec;
+  hipStream_t cs;
+  HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  launch_sweep(pl, a, cs, false);
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  HIP_OK(e);
+  if (g_graphs.size() > 64) {
+    for (auto& g : g_graphs) (void)hipGraphExecDestroy(g.exec);
+    g_graphs.clear();
+  }
+  g_graphs.push_back({pl.len, pl.cnt, pl.jb, a.max_inner, a.x, work, a.rot_count, exec});
+  (void)stream;
+  return exec;
+}
+
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev, int* rot_count_host,
                double fro2, hipStream_t stream, int max_sweeps) {
   JacArgs a;
@@ -367,15 +491,13 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
   a.nbp = pl.nbp;
   a.rows_per_chunk = pl.rows_per_chunk;
   a.n_chunks = pl.n_chunks;
+  a.round = 0;
   char* w = reinterpret_cast<char*>(work);
   a.part = reinterpret_cast<double2*>(w);
   w += (size_t)pl.n_pairs * pl.n_chunks * (2 * pl.jb) * (2 * pl.jb) * sizeof(double2);
   a.rot_prev = reinterpret_cast<int*>(w);
   a.rot_cur = a.rot_prev + pl.nbp;
   a.rot_count = rot_count_dev;
-  // relative orthogonality target just above the rounding noise of a
-  // length-len fp64 inner product; the absolute floor only guards columns
-  // that are exactly or numerically zero (|g_ij| below 1e-300 colmax2)
   a.tol = 16.0 * 1.11e-16 * std::sqrt((double)std::max(pl.len, 16));
   // columns shorter than delta ||X||_F (delta = 8 u sqrt(len)) are numerically
   // zero: below the absolute accuracy of any fp64 SVD, and they must not be
@@ -383,37 +505,13 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
   // its rank)
   const double delta = 8.0 * 1.11e-16 * std::sqrt((double)pl.len);
   a.neg2 = delta * delta * std::max(fro2, 1e-300);
-  {
-    const char* e = std::getenv("RCS_JACOBI_INNER");
-    a.max_inner = (e && std::atoi(e) > 0) ? std::atoi(e) : pl.inner;
-  }
+  a.max_inner = pl.inner;
+  const bool graphs = use_graphs() && pl.nbp > 4;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
-    hipLaunchKernelGGL(k_jac_roll, dim3(1), dim3(256), 0, stream, a.rot_prev, a.rot_cur, a.rot_count, pl.nbp,
-                       sweep == 1 ? 1 : 0);
-    HIP_LAUNCH_OK();
-    for (int r = 0; r < pl.nbp - 1; ++r) {
-      a.round = r;
-      // nominal algorithmic work of a round with every pair active: Gram and
-      // update are each n_pairs complex GEMMs of len x JP x JP
-      const double JPd = 2.0 * pl.jb;
-      const double fl = 8.0 * pl.len * JPd * JPd * pl.n_pairs;
-      const double by = 16.0 * (double)pl.len * JPd * pl.n_pairs;
-      {
-        Probe pr(kKcJacGram, stream, fl, by);
-        if (pl.jb == 16)
-          hipLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
-        else
-          hipLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
-      }
-      HIP_LAUNCH_OK();
-      {
-        Probe pr(kKcJacRotate, stream, fl, 2.0 * by);
-        if (pl.jb == 16)
-          hipLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
-        else
-          hipLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
-      }
-      HIP_LAUNCH_OK();
+    if (graphs && sweep > 1) {
+      HIP_OK(hipGraphLaunch(sweep_graph(pl, a, work, stream), stream));
+    } else {
+      launch_sweep(pl, a, stream, sweep == 1);
     }
     HIP_OK(hipMemcpyAsync(rot_count_host, rot_count_dev, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
@@ -427,3 +525,19 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
 void jacobi_init_attributes() {}
 
 }  // namespace rcs
+
+extern "C" {
+
+rcs_status rcs_tuning_set(int32_t cnt_max, int32_t block, int32_t inner_sweeps) {
+  try {
+    rcs::tuning_set(cnt_max, block, inner_sweeps);
+  } catch (const rcs::Error& e) {
+    rcs::set_last_error(e.what());
+    return e.status;
+  }
+  return RCS_OK;
+}
+
+void rcs_tuning_clear(void) { rcs::tuning_clear(); }
+
+}  // extern "C"

@@ -25,10 +25,8 @@ struct ChainArgs {
   int S, dl, dr, ntiles;
 };
 
-__global__ __launch_bounds__(GT_THREADS) void k_chain_gemm(ChainArgs a) {
-  __shared__ SmemC64 sm;
-  __shared__ double rowsum[2][GT_M];
-  const int tn = blockIdx.x, tm = blockIdx.y, s = blockIdx.z;
+__device__ inline void chain_gemm_tile(const ChainArgs& a, int tn, int tm, int s, SmemC64& sm,
+                                       double (*rowsum)[GT_M]) {
   const int m0 = tm * GT_M, n0 = tn * GT_N;
   const int dl = a.dl, dr = a.dr;
   auto fa = [&](int m, int k) -> double2 {
@@ -83,6 +81,30 @@ __global__ __launch_bounds__(GT_THREADS) void k_chain_gemm(ChainArgs a) {
   }
 }
 
+__global__ __launch_bounds__(GT_THREADS) void k_chain_gemm(ChainArgs a) {
+  __shared__ SmemC64 sm;
+  __shared__ double rowsum[2][GT_M];
+  chain_gemm_tile(a, blockIdx.x, blockIdx.y, blockIdx.z, sm, rowsum);
+}
+
+// Grouped form for a batch of states: group g owns tiles [tile0[g],
+// tile0[g+1]) of the launch (ntiles x mtiles of its own GEMM).
+struct ChainGroup {
+  ChainArgs a;
+  int tile0, mtiles;
+};
+
+__global__ __launch_bounds__(GT_THREADS) void k_chain_gemm_grouped(const ChainGroup* groups, int ng) {
+  __shared__ SmemC64 sm;
+  __shared__ double rowsum[2][GT_M];
+  const int t = blockIdx.x;
+  int g = 0;
+  while (g + 1 < ng && groups[g + 1].tile0 <= t) ++g;
+  const ChainGroup& G = groups[g];
+  const int local = t - G.tile0;
+  chain_gemm_tile(G.a, local % G.a.ntiles, local / G.a.ntiles, blockIdx.z, sm, rowsum);
+}
+
 struct DecideArgs {
   const double* part;
   int S, ntiles, site, qubit, last, mode;
@@ -95,9 +117,7 @@ struct DecideArgs {
   double2* amps;           // mode 1 output
 };
 
-__global__ void k_decide(DecideArgs a) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= a.S) return;
+__device__ inline void decide_one(const DecideArgs& a, int m) {
   if (a.mode == 0) {
     double p0 = 0.0, p1 = 0.0;
     const double* q0 = a.part + (int64_t)m * a.ntiles;
@@ -117,6 +137,17 @@ __global__ void k_decide(DecideArgs a) {
     a.sel[m] = (int8_t)b;
     if (a.last) a.amps[m] = a.wlast[(int64_t)m * 2 + b];
   }
+}
+
+__global__ void k_decide(DecideArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < a.S) decide_one(a, m);
+}
+
+__global__ void k_decide_grouped(const DecideArgs* groups) {
+  const DecideArgs& a = groups[blockIdx.y];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < a.S) decide_one(a, m);
 }
 
 void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed, int mode,
@@ -176,6 +207,111 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
       HIP_LAUNCH_OK();
     }
   }
+}
+
+// Batched sampling: for every shot pass and site index, one grouped GEMM
+// launch over all states that have that site and one grouped decision
+// launch.  All launch descriptors are built on the host up front and
+// uploaded once, so the whole sequence is captured into a HIP graph (on a
+// private stream) and replayed.
+void run_chain_batch(rcs_state_s** states, int n, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
+                     double* log2p_dev, hipStream_t user_stream) {
+  if (n == 0 || n_shots == 0) return;
+  int maxd = 1, maxn = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int d : states[i]->dims) maxd = std::max(maxd, d);
+    maxn = std::max(maxn, states[i]->n);
+  }
+  // shots per state per pass, so that all W buffers together stay <= 4 GiB
+  int64_t S0 = ((int64_t)1 << 32) / ((int64_t)n * 2 * 2 * maxd * 16);
+  S0 = std::max<int64_t>(64, std::min<int64_t>(16384, S0 / 64 * 64));
+  S0 = std::min<int64_t>(S0, round_up((int64_t)n_shots, 64));
+  const int ntiles_max = ceil_div(maxd, GT_N);
+  DevBuf w0, w1, part, sel;
+  w0.ensure((size_t)n * S0 * 2 * maxd * sizeof(double2));
+  w1.ensure((size_t)n * S0 * 2 * maxd * sizeof(double2));
+  part.ensure((size_t)n * 2 * S0 * ntiles_max * sizeof(double));
+  sel.ensure((size_t)n * S0);
+  const int passes = (int)((n_shots + S0 - 1) / S0);
+  // descriptors: per (pass, site): groups of states with site k
+  std::vector<ChainGroup> cg;
+  std::vector<DecideArgs> dg;
+  struct Launch {
+    size_t c0, d0;
+    int ng, tiles, S;
+  };
+  std::vector<Launch> launches;
+  for (int pass = 0; pass < passes; ++pass) {
+    const uint64_t b0 = (uint64_t)pass * S0;
+    const int S = (int)std::min<uint64_t>((uint64_t)S0, n_shots - b0);
+    for (int k = 0; k < maxn; ++k) {
+      Launch L{cg.size(), dg.size(), 0, 0, S};
+      for (int i = 0; i < n; ++i) {
+        rcs_state_s& st = *states[i];
+        if (k >= st.n) continue;
+        double2* wb0 = w0.as<double2>() + (size_t)i * S0 * 2 * maxd;
+        double2* wb1 = w1.as<double2>() + (size_t)i * S0 * 2 * maxd;
+        ChainGroup g;
+        g.a.wprev = (k == 0) ? nullptr : ((k - 1) & 1 ? wb1 : wb0);
+        g.a.sel = sel.as<int8_t>() + (size_t)i * S0;
+        g.a.site = st.site[k];
+        g.a.wout = (k & 1) ? wb1 : wb0;
+        g.a.part = part.as<double>() + (size_t)i * 2 * S0 * ntiles_max;
+        g.a.S = S;
+        g.a.dl = st.dims[k];
+        g.a.dr = st.dims[k + 1];
+        g.a.ntiles = ceil_div(g.a.dr, GT_N);
+        g.mtiles = ceil_div(S, GT_M);
+        g.tile0 = L.tiles;
+        L.tiles += g.a.ntiles * g.mtiles;
+        cg.push_back(g);
+        DecideArgs d;
+        d.part = g.a.part;
+        d.S = S;
+        d.ntiles = g.a.ntiles;
+        d.site = k;
+        d.qubit = st.pi[k];
+        d.last = (k == st.n - 1);
+        d.mode = 0;
+        d.seed = seed;
+        d.shot0 = b0;
+        d.sel = sel.as<int8_t>() + (size_t)i * S0;
+        d.bits = bits_dev + (uint64_t)i * n_shots + b0;
+        d.log2p = log2p_dev ? log2p_dev + (uint64_t)i * n_shots + b0 : nullptr;
+        d.inbits = nullptr;
+        d.wlast = g.a.wout;
+        d.amps = nullptr;
+        dg.push_back(d);
+        L.ng += 1;
+      }
+      if (L.ng) launches.push_back(L);
+    }
+  }
+  DevBuf dcg, ddg;
+  dcg.ensure(cg.size() * sizeof(ChainGroup));
+  ddg.ensure(dg.size() * sizeof(DecideArgs));
+  HIP_OK(hipMemcpyAsync(dcg.p, cg.data(), cg.size() * sizeof(ChainGroup), hipMemcpyHostToDevice, user_stream));
+  HIP_OK(hipMemcpyAsync(ddg.p, dg.data(), dg.size() * sizeof(DecideArgs), hipMemcpyHostToDevice, user_stream));
+  HIP_OK(hipStreamSynchronize(user_stream));
+  hipStream_t cs;
+  HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (const Launch& L : launches) {
+    hipLaunchKernelGGL(k_chain_gemm_grouped, dim3(L.tiles, 1, 2), dim3(GT_THREADS), 0, cs,
+                       dcg.as<ChainGroup>() + L.c0, L.ng);
+    hipLaunchKernelGGL(k_decide_grouped, dim3(ceil_div(L.S, 256), L.ng), dim3(256), 0, cs,
+                       ddg.as<DecideArgs>() + L.d0);
+  }
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ce == hipSuccess) ce = hipGraphLaunch(exec, cs);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(cs);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  HIP_OK(ce);
 }
 
 __global__ void k_abs2(const double2* z, uint64_t m, double* out) {

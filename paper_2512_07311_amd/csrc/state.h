@@ -80,6 +80,10 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
                uint64_t* bits_dev, double* log2p_dev, const uint64_t* in_bits_dev,
                double* amps_dev);
 
+// Shots from several states: grouped launches captured in one HIP graph.
+void run_chain_batch(rcs_state_s** states, int n, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
+                     double* log2p_dev, hipStream_t user_stream);
+
 // out[i] = |z[i]|^2.
 void abs2_to(const double2* z, uint64_t m, double* out, hipStream_t stream);
 

@@ -111,13 +111,18 @@ def test_invalid_build_arguments(env):
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 @pytest.mark.parametrize("rows,cols,cyc,seed,chi,eps", [(3, 4, 8, 1, 64, 0.0), (4, 5, 10, 3, 16, 1e-10)])
 def test_reduced_precision_build_error_budget(env, precision, rows, cols, cyc, seed, chi, eps):
-    """complex64 / split-bf16 contractions with fp64 SVD: amplitudes within
-    2e-4 (normwise relative) of the fp64 oracle on the same schedule."""
+    """complex64 / split-bf16 contractions with fp64 SVD against the fp64
+    oracle on the same schedule: 2e-4 (normwise relative) for exact builds;
+    truncated builds amplify the contraction error like fp64 round-off, so
+    their bar is the per-contraction error (2^-22 for complex64, 2^-15 for
+    the three-product bf16 split) times the summed cut conditioning."""
     rcs, torch = env
     c = rcs.Circuit(rows, cols, cyc, seed)
     g = rcs.State.build(c, chi, eps, contraction=precision)
     om = mps.build(oc.Circuit(rows, cols, cyc, seed), chi, eps)
     b = inputs.random_bitstrings(c.n, 1000, seed=23)
     err = normwise_rel(_amps(torch, g, b), om.amplitudes(b))
-    assert err < 2e-4, err
+    u = 2.0 ** -22 if precision == "c64" else 2.0 ** -15
+    bar = 2e-4 if eps == 0.0 else max(2e-4, u * truncated_tolerance(om) / 1e-13)
+    assert err < bar, (err, bar)
     assert g.info().canonical == 1
