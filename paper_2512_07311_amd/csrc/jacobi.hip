@@ -32,7 +32,7 @@
 
 namespace rcs {
 
-constexpr int TR = 16;        // rows per wave tile
+constexpr int TR = 16;        // rows per wave tile (four 4-row MFMA k steps)
 
 __device__ inline int rr_block(int slot, int round, int nbp) {
   return slot == 0 ? 0 : ((slot - 1 + round) % (nbp - 1)) + 1;
@@ -65,98 +65,209 @@ __device__ inline int pair_col(int c, int bi, int bj) {
   return c < JP / 2 ? bi * (JP / 2) + c : bj * (JP / 2) + (c - JP / 2);
 }
 
-// Load a 16-row x JP-column tile of Y_p (rows row0.., masked at rend) into a
-// wave's LDS tile.  Each lane takes 16*JP/64 consecutive rows of one column.
+// Lane's element of every 16-column block of Y_p at one row (zero past
+// rend).  The lane's column within a block is lane % 16, so a load
+// instruction covers 16 columns x 4 consecutive rows.
 template <int JP>
-__device__ inline void load_tile(const double2* x, int ldx, int bi, int bj, int row0, int rend,
-                                 double2 (*tile)[JP + 1], int lane) {
-  constexpr int LPC = 64 / JP;          // lanes per column
-  constexpr int RPL = TR / LPC;         // rows per lane
-  const int c = lane / LPC, h = (lane % LPC) * RPL;
-  const double2* col = x + (int64_t)pair_col<JP>(c, bi, bj) * ldx;
+__device__ inline void load_row(const double2* x, int ldx, int bi, int bj, int row, int rend,
+                                double2 (&v)[JP / 16], int lane) {
 #pragma unroll
-  for (int t = 0; t < RPL; ++t) {
-    const int r = row0 + h + t;
-    tile[h + t][c] = (r < rend) ? col[r] : make_double2(0.0, 0.0);
+  for (int cb = 0; cb < JP / 16; ++cb) {
+    const int col = pair_col<JP>(cb * 16 + (lane & 15), bi, bj);
+    v[cb] = row < rend ? x[(int64_t)col * ldx + row] : make_double2(0.0, 0.0);
   }
 }
 
-// Partial Grams.  The JP x JP output is split into 16x16 MFMA blocks; wave w
-// owns blocks w, w+4, ... and all waves walk the chunk's rows together
-// through per-wave LDS tiles (every wave reads every tile).
+// Partial Grams.  Waves split the chunk's rows (16-row tiles, interleaved)
+// and each accumulates the NB(NB+1)/2 upper 16x16 blocks of Y^H Y on the
+// matrix cores straight from registers; the four waves are then reduced in
+// the fixed order ((w3 + w2) + w1) + w0 through LDS.
 template <int JP>
 __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
-  constexpr int NB = JP / 16, NBLK = NB * NB, PER = (NBLK + 3) / 4;
-  __shared__ double2 tile[4][TR][JP + 1];
+  constexpr int NB = JP / 16, NU = NB * (NB + 1) / 2;
+  __shared__ double red[NU * 8][64];
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int rbeg = chunk * a.rows_per_chunk;
   const int rend = min(a.len, rbeg + a.rows_per_chunk);
-  const int ngroups = (rend - rbeg + TR - 1) / TR;
-  double4_t gr[PER], gi[PER];
+  const int ntiles = (rend - rbeg + TR - 1) / TR;
+  double4_t gr[NU], gi[NU];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    gr[i] = double4_t{0, 0, 0, 0};
-    gi[i] = double4_t{0, 0, 0, 0};
+  for (int u = 0; u < NU; ++u) {
+    gr[u] = double4_t{0, 0, 0, 0};
+    gi[u] = double4_t{0, 0, 0, 0};
   }
-  for (int g0 = 0; g0 < ngroups; g0 += 4) {
-    const int g = g0 + w;
-    if (g < ngroups) load_tile<JP>(a.x, a.ldx, bi, bj, rbeg + g * TR, rend, tile[w], lane);
-    __syncthreads();
-    const int nt_here = min(4, ngroups - g0);
-    for (int tt = 0; tt < nt_here; ++tt) {
+  double2 cur[4][NB], nxt[4][NB];
+  const int rsub = lane >> 4;
+  if (w < ntiles) {
 #pragma unroll
-      for (int kk = 0; kk < TR; kk += 4) {
-        const int r = kk + (lane >> 4);
+    for (int ks = 0; ks < 4; ++ks)
+      load_row<JP>(a.x, a.ldx, bi, bj, rbeg + w * TR + 4 * ks + rsub, rend, cur[ks], lane);
+  }
+  for (int t = w; t < ntiles; t += 4) {
+    if (t + 4 < ntiles) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int blk = w + 4 * q;
-          if (blk < NBLK) {
-            const int mb = blk / NB, nb = blk % NB;
-            const double2 ym = tile[tt][r][mb * 16 + (lane & 15)];
-            const double2 yn = tile[tt][r][nb * 16 + (lane & 15)];
-            gr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.x, gr[q], 0, 0, 0);
-            gr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.y, yn.y, gr[q], 0, 0, 0);
-            gi[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.y, gi[q], 0, 0, 0);
-            gi[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ym.y, yn.x, gi[q], 0, 0, 0);
-          }
+      for (int ks = 0; ks < 4; ++ks)
+        load_row<JP>(a.x, a.ldx, bi, bj, rbeg + (t + 4) * TR + 4 * ks + rsub, rend, nxt[ks], lane);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      int u = 0;
+#pragma unroll
+      for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+        for (int nb = mb; nb < NB; ++nb, ++u) {
+          const double2 ym = cur[ks][mb], yn = cur[ks][nb];
+          gr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.x, gr[u], 0, 0, 0);
+          gr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.y, yn.y, gr[u], 0, 0, 0);
+          gi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.y, gi[u], 0, 0, 0);
+          gi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ym.y, yn.x, gi[u], 0, 0, 0);
         }
-      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) cur[ks][cb] = nxt[ks][cb];
+  }
+  for (int src = 3; src >= 1; --src) {
+    if (w == src) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double vr = gr[u][r], vi = gi[u][r];
+          if (src < 3) {
+            vr += red[u * 8 + r][lane];
+            vi += red[u * 8 + 4 + r][lane];
+          }
+          red[u * 8 + r][lane] = vr;
+          red[u * 8 + 4 + r][lane] = vi;
+        }
     }
     __syncthreads();
   }
+  if (w != 0) return;
   double2* part = a.part + ((int64_t)p * a.n_chunks + chunk) * JP * JP;
+  int u = 0;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int blk = w + 4 * q;
-    if (blk < NBLK) {
-      const int mb = blk / NB, nb = blk % NB;
+  for (int mb = 0; mb < NB; ++mb)
+#pragma unroll
+    for (int nb = mb; nb < NB; ++nb, ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        const double vr = gr[u][r] + red[u * 8 + r][lane];
+        const double vi = gi[u][r] + red[u * 8 + 4 + r][lane];
         const int row = mb * 16 + f64_row(lane, r), col = nb * 16 + (lane & 15);
-        part[row * JP + col] = make_double2(gr[q][r], gi[q][r]);
+        part[row * JP + col] = make_double2(vr, vi);
+        if (mb != nb) part[col * JP + row] = make_double2(vr, -vi);
       }
-    }
-  }
 }
 
-// Sum partial Grams (fixed order), diagonalise by cyclic two-sided Jacobi,
-// rotate this chunk's rows.  LDS: V, and G aliased with the row tiles (G is
-// dead once V is known).
+// 1/sqrt(x) for normal positive x: hardware estimate plus two Newton steps
+// (each doubles the correct bits; the estimate carries about 23), i.e.
+// within a couple of ulps.
+__device__ inline double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * r, r, 0.5);
+  r = fma(r, e, r);
+  e = fma(-h * r, r, 0.5);
+  return fma(r, e, r);
+}
+
+// Plane rotation J = [[c, s e], [-s conj(e), c]] (rows: old columns i < j,
+// columns: new) that (nearly) zeroes G_ij of the Hermitian 2x2 [[gii, g],
+// [conj g, gjj]] in J^H G J; the identity when the pair is already
+// orthogonal to tol or either column is negligible.
+//
+// Only unitarity has to hold to fp64 accuracy: the angle may be a few
+// 1e-8 off (it leaves an off-diagonal of that relative size, which the
+// next sweep's fresh Gram sees and removes, so convergence stays
+// quadratic).  Hence e = g * rsq(|g|^2) with the raw hardware estimate
+// (exact phase, modulus within ~2^-23 of one), tan(theta) in fp32 from
+// tau = (gjj - gii) / (2|g|) (the smaller-angle root, |t| <= 1), and
+// c = 1/sqrt(1 + t^2 |e|^2) refined in fp64, s = t c, which makes
+// c^2 + s^2 |e|^2 = 1 to rounding.  Branch-free: inactive pairs select the
+// identity.
+struct Rot {
+  double c, s, ex, ey;
+};
+__device__ inline bool rot_active(double gii, double gjj, double h2, double tol, double neg2) {
+  return gii > neg2 && gjj > neg2 && h2 > 1e-300 && h2 > tol * tol * gii * gjj;
+}
+__device__ inline Rot jac_rot(double gii, double gjj, double2 g, double tol, double neg2) {
+  const double h2 = g.x * g.x + g.y * g.y;
+  const bool act = rot_active(gii, gjj, h2, tol, neg2);
+  const double rh = __builtin_amdgcn_rsq(fmax(h2, 1e-300));
+  const double tau = (gjj - gii) * (0.5 * rh);
+  const float tf = (float)fabs(tau);
+  const float t32 = tf > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(tf)
+                               : __builtin_amdgcn_rcpf(tf + __builtin_amdgcn_sqrtf(fmaf(tf, tf, 1.0f)));
+  const double t = tau < 0.0 ? -(double)t32 : (double)t32;
+  const double ex = g.x * rh, ey = g.y * rh;
+  const double c = rsqrt_nr(fma(t * t, ex * ex + ey * ey, 1.0));
+  Rot r;
+  r.c = act ? c : 1.0;
+  r.s = act ? t * c : 0.0;
+  r.ex = act ? ex : 1.0;
+  r.ey = act ? ey : 0.0;
+  return r;
+}
+
+// With a = s e:
+// right action (X J):  x_i' = c x_i - conj(a) x_j,  x_j' = a x_i + c x_j;
+// left action (J^H X): x_i' = c x_i - a x_j,        x_j' = conj(a) x_i + c x_j.
+__device__ inline void rot_right(const Rot& r, double2& xi, double2& xj) {
+  const double ax = r.s * r.ex, ay = r.s * r.ey;
+  const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, ay * xj.y)), fma(r.c, xi.y, fma(ay, xj.x, -ax * xj.y)));
+  xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, -ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, ay * xi.x)));
+  xi = ni;
+}
+__device__ inline void rot_left(const Rot& r, double2& xi, double2& xj) {
+  const double ax = r.s * r.ex, ay = r.s * r.ey;
+  const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, -ay * xj.y)), fma(r.c, xi.y, -fma(ax, xj.y, ay * xj.x)));
+  xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, -ay * xi.x)));
+  xi = ni;
+}
+
+// Members (i < j) of pair q in round-robin round `round` of JP columns, and
+// the pair that column c belongs to in that round.
+template <int JP>
+__device__ inline void rr_pair(int q, int round, int& i, int& j) {
+  const int u = q == 0 ? 0 : ((q - 1 + round) % (JP - 1)) + 1;
+  const int v = ((JP - 2 - q + round) % (JP - 1)) + 1;
+  i = min(u, v);
+  j = max(u, v);
+}
+template <int JP>
+__device__ inline int rr_pair_of(int c, int round) {
+  const int slot = c == 0 ? 0 : ((c - 1 - round + 2 * (JP - 1)) % (JP - 1)) + 1;
+  return min(slot, JP - 1 - slot);
+}
+
+// Sum partial Grams (fixed order), diagonalise the JP x JP Hermitian G_p by
+// cyclic two-sided Jacobi in LDS (every workgroup of a pair computes the
+// same unitary V_p), and rotate this chunk's rows, Y_p <- Y_p V_p, on the
+// matrix cores.
+//
+// Inner solve: a round applies JP/2 disjoint rotations at once; thread jobs
+// are the (JP/2)^2 blocks G[pair a, pair b] <- J_a^H G[a, b] J_b and
+// V[rows of a, pair b] <- V J_b, done in place (each entry belongs to one
+// job per round).  The diagonal and the next round's pair entries are
+// handed on through small double-buffered arrays, so a round needs one
+// barrier.
 template <int JP>
 __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
-  constexpr int GS = JP + 1, NP = JP / 2, NB = JP / 16;
-  constexpr int G_BYTES = JP * GS * 16, T_BYTES = 4 * TR * GS * 16;
+  constexpr int GS = JP + 1, NP = JP / 2, NB = JP / 16, JOBS = NP * NP / 256;
+  static_assert(NP * NP % 256 == 0, "block jobs must tile the workgroup");
+  __shared__ double2 G[JP][GS];
   __shared__ double2 V[JP][GS];
-  __shared__ __align__(16) char gt_raw[G_BYTES > T_BYTES ? G_BYTES : T_BYTES];
-  __shared__ double rc[NP], rs[NP];
-  __shared__ double2 re_[NP];
-  __shared__ int ri[NP], rj[NP];
+  __shared__ double dd[2][JP];
+  __shared__ double2 od[2][NP];
+  __shared__ unsigned char tb_i[JP - 1][NP], tb_j[JP - 1][NP], tb_q[JP - 1][JP];
   __shared__ int any_flag;
-  double2 (*G)[GS] = reinterpret_cast<double2 (*)[GS]>(gt_raw);
-  double2 (*tile)[TR][GS] = reinterpret_cast<double2 (*)[TR][GS]>(gt_raw);
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
@@ -174,133 +285,129 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
     V[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) any_flag = 0;
+  // round-robin tables: members of pair q and the pair of column c, per round
+  for (int e = tid; e < (JP - 1) * NP; e += 256) {
+    const int rd = e / NP, q = e % NP;
+    int i, j;
+    rr_pair<JP>(q, rd, i, j);
+    tb_i[rd][q] = (unsigned char)i;
+    tb_j[rd][q] = (unsigned char)j;
+  }
+  for (int e = tid; e < (JP - 1) * JP; e += 256) tb_q[e / JP][e % JP] = (unsigned char)rr_pair_of<JP>(e % JP, e / JP);
   __syncthreads();
   for (int e = tid; e < JP * JP; e += 256) {
     const int i = e / JP, j = e % JP;
-    if (i < j) {
-      const double h = sqrt(cabs2(G[i][j]));
-      const double d = sqrt(fabs(G[i][i].x * G[j][j].x));
-      if (h > a.tol * d && G[i][i].x > a.neg2 && G[j][j].x > a.neg2) any_flag = 1;
-    }
+    if (i < j && rot_active(G[i][i].x, G[j][j].x, G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y, a.tol, a.neg2))
+      any_flag = 1;
+  }
+  for (int c = tid; c < JP; c += 256) dd[0][c] = G[c][c].x;
+  for (int q = tid; q < NP; q += 256) {
+    int i, j;
+    rr_pair<JP>(q, 0, i, j);
+    od[0][q] = G[i][j];
   }
   __syncthreads();
   if (!any_flag) return;
   const double tol_in = 0.5 * a.tol, neg2 = a.neg2;
-  for (int sweep = 0; sweep < a.max_inner; ++sweep) {
-    for (int round = 0; round < JP - 1; ++round) {
-      if (tid < NP) {
-        int i = (tid == 0) ? 0 : ((tid - 1 + round) % (JP - 1)) + 1;
-        int j = ((JP - 2 - tid + round) % (JP - 1)) + 1;
-        if (i > j) {
-          const int t = i;
-          i = j;
-          j = t;
+  const int rounds = a.max_inner * (JP - 1);
+  int buf = 0;
+  int round = 0;
+  for (int R = 0; R < rounds; ++R) {
+    const int nround = round + 1 == JP - 1 ? 0 : round + 1;
+    const int pb = tid % NP;
+    const int ib = tb_i[round][pb], jb = tb_j[round][pb];
+    const Rot rb = jac_rot(dd[buf][ib], dd[buf][jb], od[buf][pb], tol_in, neg2);
+#pragma unroll
+    for (int k = 0; k < JOBS; ++k) {
+      const int pa = (tid + 256 * k) / NP;
+      const int ia = tb_i[round][pa], ja = tb_j[round][pa];
+      const Rot ra = jac_rot(dd[buf][ia], dd[buf][ja], od[buf][pa], tol_in, neg2);
+      double2 g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
+      rot_right(rb, g00, g01);
+      rot_right(rb, g10, g11);
+      rot_left(ra, g00, g10);
+      rot_left(ra, g01, g11);
+      G[ia][ib] = g00;
+      G[ia][jb] = g01;
+      G[ja][ib] = g10;
+      G[ja][jb] = g11;
+      double2 v0 = V[ia][ib], v1 = V[ia][jb];
+      rot_right(rb, v0, v1);
+      V[ia][ib] = v0;
+      V[ia][jb] = v1;
+      v0 = V[ja][ib];
+      v1 = V[ja][jb];
+      rot_right(rb, v0, v1);
+      V[ja][ib] = v0;
+      V[ja][jb] = v1;
+      // hand on the diagonal and the next round's pair entries
+      const int rows[2] = {ia, ja}, cols[2] = {ib, jb};
+      const int qr[2] = {tb_q[nround][ia], tb_q[nround][ja]};
+      const int qc[2] = {tb_q[nround][ib], tb_q[nround][jb]};
+      const double2 vals[2][2] = {{g00, g01}, {g10, g11}};
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int r = rows[x], c = cols[y];
+          if (r == c) dd[buf ^ 1][r] = vals[x][y].x;
+          else if (r < c && qr[x] == qc[y]) od[buf ^ 1][qr[x]] = vals[x][y];
         }
-        ri[tid] = i;
-        rj[tid] = j;
-        const double gii = G[i][i].x, gjj = G[j][j].x;
-        const double2 g = G[i][j];
-        const double h = sqrt(cabs2(g));
-        double c = 1.0, s = 0.0;
-        double2 e = make_double2(1.0, 0.0);
-        if (h > 1e-300 && gii > neg2 && gjj > neg2 && h > tol_in * sqrt(gii * gjj)) {
-          const double tau = (gjj - gii) / (2.0 * h);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          e = make_double2(g.x / h, g.y / h);
-        }
-        rc[tid] = c;
-        rs[tid] = s;
-        re_[tid] = e;
-      }
-      __syncthreads();
-      for (int job = tid; job < NP * JP; job += 256) {   // G <- G J, V <- V J
-        const int q = job / JP, r = job % JP;
-        const double s = rs[q];
-        if (s == 0.0) continue;
-        const int i = ri[q], j = rj[q];
-        const double c = rc[q];
-        const double2 e = re_[q], ec = cconj(e);
-        const double2 gi = G[r][i], gj = G[r][j];
-        const double2 t1 = cmul(ec, gj), t2 = cmul(e, gi);
-        G[r][i] = make_double2(c * gi.x - s * t1.x, c * gi.y - s * t1.y);
-        G[r][j] = make_double2(s * t2.x + c * gj.x, s * t2.y + c * gj.y);
-        const double2 vi = V[r][i], vj = V[r][j];
-        const double2 u1 = cmul(ec, vj), u2 = cmul(e, vi);
-        V[r][i] = make_double2(c * vi.x - s * u1.x, c * vi.y - s * u1.y);
-        V[r][j] = make_double2(s * u2.x + c * vj.x, s * u2.y + c * vj.y);
-      }
-      __syncthreads();
-      for (int job = tid; job < NP * JP; job += 256) {   // G <- J^H G
-        const int q = job / JP, col = job % JP;
-        const double s = rs[q];
-        if (s == 0.0) continue;
-        const int i = ri[q], j = rj[q];
-        const double c = rc[q];
-        const double2 e = re_[q], ec = cconj(e);
-        const double2 gi = G[i][col], gj = G[j][col];
-        const double2 t1 = cmul(e, gj), t2 = cmul(ec, gi);
-        G[i][col] = make_double2(c * gi.x - s * t1.x, c * gi.y - s * t1.y);
-        G[j][col] = make_double2(s * t2.x + c * gj.x, s * t2.y + c * gj.y);
-      }
-      __syncthreads();
     }
-    if (sweep + 1 == a.max_inner) break;
-    if (tid == 0) any_flag = 0;
-    __syncthreads();
-    for (int e = tid; e < JP * JP; e += 256) {
-      const int i = e / JP, j = e % JP;
-      if (i < j) {
-        const double h = sqrt(cabs2(G[i][j]));
-        const double d = sqrt(fabs(G[i][i].x * G[j][j].x));
-        if (h > tol_in * d && G[i][i].x > neg2 && G[j][j].x > neg2) any_flag = 1;
-      }
-    }
-    __syncthreads();
-    if (!any_flag) break;
+    buf ^= 1;
+    round = nround;
     __syncthreads();
   }
-  __syncthreads();   // G is dead from here on: its LDS becomes the row tiles
+  // Y_p <- Y_p V_p: waves take 16-row tiles; A operand straight from global
+  // (16 consecutive rows of one column per 16 lanes), B = V from LDS.
   const int rbeg = chunk * a.rows_per_chunk;
   const int rend = min(a.len, rbeg + a.rows_per_chunk);
-  const int ngroups = (rend - rbeg + TR - 1) / TR;
-  for (int g0 = 0; g0 < ngroups; g0 += 4) {
-    const int g = g0 + w;
-    const int row0 = rbeg + g * TR;
-    if (g < ngroups) load_tile<JP>(a.x, a.ldx, bi, bj, row0, rend, tile[w], lane);
-    __syncthreads();
-    if (g < ngroups) {
-      double4_t cr[NB], ci[NB];
+  const int ntiles = (rend - rbeg + TR - 1) / TR;
+  constexpr int KS = JP / 4;
+  double2 cur[KS], nxt[KS];
+  const int m = lane & 15, ksub = lane >> 4;
+  auto load_tile_regs = [&](int t, double2 (&v)[KS]) {
+    const int row = rbeg + t * TR + m;
 #pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        cr[t] = double4_t{0, 0, 0, 0};
-        ci[t] = double4_t{0, 0, 0, 0};
-      }
-#pragma unroll
-      for (int kk = 0; kk < JP; kk += 4) {
-        const int k = kk + (lane >> 4);
-        const double2 y = tile[w][lane & 15][k];
-#pragma unroll
-        for (int nt = 0; nt < NB; ++nt) {
-          const double2 v = V[k][nt * 16 + (lane & 15)];
-          cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.x, cr[nt], 0, 0, 0);
-          cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, v.y, cr[nt], 0, 0, 0);
-          ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.y, ci[nt], 0, 0, 0);
-          ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, v.x, ci[nt], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int nt = 0; nt < NB; ++nt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = row0 + f64_row(lane, r);
-          const int col = nt * 16 + (lane & 15);
-          if (row < rend)
-            a.x[(int64_t)pair_col<JP>(col, bi, bj) * a.ldx + row] = make_double2(cr[nt][r], ci[nt][r]);
-        }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int col = pair_col<JP>(4 * ks + ksub, bi, bj);
+      v[ks] = row < rend ? a.x[(int64_t)col * a.ldx + row] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
+  };
+  if (w < ntiles) load_tile_regs(w, cur);
+  for (int t = w; t < ntiles; t += 4) {
+    if (t + 4 < ntiles) load_tile_regs(t + 4, nxt);
+    double4_t cr[NB], ci[NB];
+#pragma unroll
+    for (int nt = 0; nt < NB; ++nt) {
+      cr[nt] = double4_t{0, 0, 0, 0};
+      ci[nt] = double4_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const double2 y = cur[ks];
+      const int k = 4 * ks + ksub;
+#pragma unroll
+      for (int nt = 0; nt < NB; ++nt) {
+        const double2 v = V[k][nt * 16 + m];
+        cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.x, cr[nt], 0, 0, 0);
+        cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, v.y, cr[nt], 0, 0, 0);
+        ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.y, ci[nt], 0, 0, 0);
+        ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, v.x, ci[nt], 0, 0, 0);
+      }
+    }
+    const int row0 = rbeg + t * TR;
+#pragma unroll
+    for (int nt = 0; nt < NB; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + f64_row(lane, r);
+        const int col = nt * 16 + m;
+        if (row < rend)
+          a.x[(int64_t)pair_col<JP>(col, bi, bj) * a.ldx + row] = make_double2(cr[nt][r], ci[nt][r]);
+      }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) cur[ks] = nxt[ks];
   }
   if (chunk == 0 && tid == 0) {
     a.rot_cur[bi] = 1;
@@ -358,7 +465,7 @@ void tuning_clear() {
 }
 
 static void tuned(int cnt, int* jb, int* inner) {
-  *jb = cnt >= 512 ? 32 : 16;
+  *jb = 16;
   *inner = 1;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -390,7 +497,12 @@ JacobiPlan jacobi_plan(int len, int cnt, int jb) {
   pl.nbp = std::max(2, nb + (nb & 1));
   pl.cnt_pad = pl.nbp * jb;
   pl.n_pairs = pl.nbp / 2;
-  const int target_chunks = std::max(1, 256 / pl.n_pairs);
+  static const int wgs = [] {
+    const char* e = std::getenv("RCS_JACOBI_WGS");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 64 && v <= 4096 ? v : 256;
+  }();
+  const int target_chunks = std::max(1, wgs / pl.n_pairs);
   const int max_chunks = ceil_div(len, 64);
   pl.n_chunks = std::max(1, std::min(target_chunks, max_chunks));
   pl.rows_per_chunk = (int)round_up(ceil_div(len, pl.n_chunks), TR);
