@@ -92,6 +92,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    # the state build reports its progress on stderr every 20 s
+    os.environ.setdefault("RCS_PROGRESS", "20")
     import numpy as np
     import torch
     if not torch.cuda.is_available():
@@ -116,7 +118,9 @@ def main():
             tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1)
             st = rcs.State.build(tc, tr["chi"], tr["eps"], log_spectra=True)
             X, Y = learn.dataset(st.spectra(), tc.n, tr["cycles"], torch)
+            print("bench: %d training spectra logged" % X.shape[0], file=sys.stderr, flush=True)
             mlp_w, _ = learn.train(X, Y, torch, steps=1500, batch=256, seed=args.seed)
+            print("bench: rank network trained", file=sys.stderr, flush=True)
             del st
         kw["mlp_weights"] = mlp_w
     bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
@@ -125,10 +129,13 @@ def main():
 
     def step():
         st = rcs.State.build(circ, wl["chi"], wl["eps"], stream=stream, max_ops=args.max_ops, **kw)
+        print("bench: state built in %.1f s" % st.info().build_seconds, file=sys.stderr, flush=True)
         t_b = time.time()
         st.sample(bits, log2p, seed=1003)
         x, se = rcs.xeb_log2(circ.n, log2p)
         torch.cuda.synchronize()
+        print("bench: %d shots sampled and scored in %.2f s" % (shots, time.time() - t_b), file=sys.stderr,
+              flush=True)
         return st, time.time() - t_b, x, se
 
     for _ in range(args.warmup):

@@ -989,7 +989,20 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
   }
   const int nops = (int)c.ops.size();
   const int stop = (o.max_ops < 0) ? nops : std::min(nops, o.max_ops);
+  // optional progress lines on stderr (RCS_PROGRESS = seconds between lines)
+  const char* pe = std::getenv("RCS_PROGRESS");
+  const double every = pe ? std::atof(pe) : 0.0;
+  const auto t_start = std::chrono::steady_clock::now();
+  double next_report = every;
   for (int oi = 0; oi < stop; ++oi) {
+    if (every > 0.0) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      if (el >= next_report) {
+        std::fprintf(stderr, "rcs build: op %d/%d, %.1f s\n", oi, stop, el);
+        std::fflush(stderr);
+        next_report = el + every;
+      }
+    }
     const Op& op = c.ops[oi];
     if (op.kind == 0) {
       apply_layer(st, c, op.arg);

@@ -17,6 +17,7 @@
 #include "build.h"
 #include "gemm_f32.h"
 #include "gemm_f64.h"
+#include "prof.h"
 #include "rsvd.h"
 
 namespace rcs {
@@ -293,7 +294,11 @@ void range_finder(const double2* M, int ldx, int len, int cnt, int l, int q, uin
                      (uint32_t)(seed >> 32), (uint32_t)step);
   HIP_LAUNCH_OK();
   const dim3 gy(ceil_div(l, FT_N), ceil_div(len, FT_M)), gz(ceil_div(l, FT_N), ceil_div(cnt, FT_M));
-  hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
+  {
+    // nominal work of the first sketch product M Z (complex fp32 GEMM)
+    Probe pr(kKcRange, s, 8.0 * len * (double)cnt * l, 16.0 * len * (double)cnt + 8.0 * (double)(len + cnt) * l);
+    hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
+  }
   HIP_LAUNCH_OK();
   orth(w.Q, w.ldq, len, l, w, s);
   for (int it = 0; it < q; ++it) {
