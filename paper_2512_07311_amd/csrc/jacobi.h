@@ -13,7 +13,8 @@ struct JacobiPlan {
   int nbp = 0;            // number of column blocks (even)
   int cnt_pad = 0;        // nbp * 32 columns allocated
   int n_pairs = 0;
-  int n_chunks = 0, rows_per_chunk = 0;
+  int n_chunks = 0, rows_per_chunk = 0;     // rotate pass row chunks
+  int n_gchunks = 0, rows_per_gchunk = 0;   // Gram pass row chunks
 };
 
 // jb <= 0 picks the default block width for the shape.

@@ -46,7 +46,8 @@ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
 struct JacArgs {
   double2* x;
-  int ldx, len, nbp, round, rows_per_chunk, n_chunks;
+  int ldx, len, nbp, round, rows_per_chunk, n_chunks;   // rotate chunks
+  int rows_per_gchunk, n_gchunks;                      // Gram chunks
   double2* part;      // [pair][chunk][JP][JP]
   int* rot_prev;      // [nbp] block rotated during the previous sweep
   int* rot_cur;       // [nbp] block rotated during this sweep
@@ -90,8 +91,8 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int rbeg = chunk * a.rows_per_chunk;
-  const int rend = min(a.len, rbeg + a.rows_per_chunk);
+  const int rbeg = chunk * a.rows_per_gchunk;
+  const int rend = min(a.len, rbeg + a.rows_per_gchunk);
   const int ntiles = (rend - rbeg + TR - 1) / TR;
   double4_t gr[NU], gi[NU];
 #pragma unroll
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
     __syncthreads();
   }
   if (w != 0) return;
-  double2* part = a.part + ((int64_t)p * a.n_chunks + chunk) * JP * JP;
+  double2* part = a.part + ((int64_t)p * a.n_gchunks + chunk) * JP * JP;
   int u = 0;
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb)
@@ -252,16 +253,17 @@ __device__ inline int rr_pair_of(int c, int round) {
 // same unitary V_p), and rotate this chunk's rows, Y_p <- Y_p V_p, on the
 // matrix cores.
 //
-// Inner solve: a round applies JP/2 disjoint rotations at once; thread jobs
-// are the (JP/2)^2 blocks G[pair a, pair b] <- J_a^H G[a, b] J_b and
-// V[rows of a, pair b] <- V J_b, done in place (each entry belongs to one
-// job per round).  The diagonal and the next round's pair entries are
-// handed on through small double-buffered arrays, so a round needs one
-// barrier.
+// Inner solve: a round applies JP/2 disjoint rotations at once.  Waves 0-3
+// take the (JP/2)^2 blocks G[pair a, pair b] <- J_a^H G[a, b] J_b, waves 4-7
+// the blocks V[rows of a, pair b] <- V J_b (one of each per SIMD, so their
+// latencies overlap), all in place: each entry belongs to one job per
+// round.  The diagonal and the next round's pair entries are handed on
+// through small double-buffered arrays, so a round needs one barrier.
+constexpr int ROT_THREADS = 512;
 template <int JP>
-__global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
+__global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   constexpr int GS = JP + 1, NP = JP / 2, NB = JP / 16, JOBS = NP * NP / 256;
-  static_assert(NP * NP % 256 == 0, "block jobs must tile the workgroup");
+  static_assert(NP * NP % 256 == 0, "block jobs must tile a wave group");
   __shared__ double2 G[JP][GS];
   __shared__ double2 V[JP][GS];
   __shared__ double dd[2][JP];
@@ -272,10 +274,10 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double2* part = a.part + (int64_t)p * a.n_chunks * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) {
+  const double2* part = a.part + (int64_t)p * a.n_gchunks * JP * JP;
+  for (int e = tid; e < JP * JP; e += ROT_THREADS) {
     double2 s = make_double2(0.0, 0.0);
-    for (int c = 0; c < a.n_chunks; ++c) {
+    for (int c = 0; c < a.n_gchunks; ++c) {
       const double2 t = part[(int64_t)c * JP * JP + e];
       s.x += t.x;
       s.y += t.y;
@@ -285,74 +287,96 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
     V[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) any_flag = 0;
-  // round-robin tables: members of pair q and the pair of column c, per round
-  for (int e = tid; e < (JP - 1) * NP; e += 256) {
+  // Inner schedule tables: members of pair q and the pair of column c, per
+  // round.  The first outer round of a sweep runs the full round-robin over
+  // all JP(JP-1)/2 column pairs (every block meets there, so every
+  // intra-block pair is rotated once per sweep); the other outer rounds
+  // rotate only the (JP/2)^2 cross pairs, column q of block bi against
+  // column (q + t) mod JP/2 of block bj in round t.  Every column pair is
+  // thus rotated at least once per sweep, as in cyclic Jacobi, at half the
+  // inner rounds.
+  const bool full = a.round == 0;
+  const int n_in = full ? JP - 1 : NP;
+  for (int e = tid; e < n_in * NP; e += ROT_THREADS) {
     const int rd = e / NP, q = e % NP;
     int i, j;
-    rr_pair<JP>(q, rd, i, j);
+    if (full) {
+      rr_pair<JP>(q, rd, i, j);
+    } else {
+      i = q;
+      j = NP + (q + rd) % NP;
+    }
     tb_i[rd][q] = (unsigned char)i;
     tb_j[rd][q] = (unsigned char)j;
   }
-  for (int e = tid; e < (JP - 1) * JP; e += 256) tb_q[e / JP][e % JP] = (unsigned char)rr_pair_of<JP>(e % JP, e / JP);
+  for (int e = tid; e < n_in * JP; e += ROT_THREADS) {
+    const int rd = e / JP, c = e % JP;
+    tb_q[rd][c] = (unsigned char)(full ? rr_pair_of<JP>(c, rd) : (c < NP ? c : (c - NP - rd + NP) % NP));
+  }
   __syncthreads();
-  for (int e = tid; e < JP * JP; e += 256) {
+  // only the pairs this meeting's schedule rotates decide whether it acts
+  for (int e = tid; e < JP * JP; e += ROT_THREADS) {
     const int i = e / JP, j = e % JP;
-    if (i < j && rot_active(G[i][i].x, G[j][j].x, G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y, a.tol, a.neg2))
+    if (i < j && (full || (i < NP && j >= NP)) &&
+        rot_active(G[i][i].x, G[j][j].x, G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y, a.tol, a.neg2))
       any_flag = 1;
   }
-  for (int c = tid; c < JP; c += 256) dd[0][c] = G[c][c].x;
-  for (int q = tid; q < NP; q += 256) {
-    int i, j;
-    rr_pair<JP>(q, 0, i, j);
-    od[0][q] = G[i][j];
-  }
+  for (int c = tid; c < JP; c += ROT_THREADS) dd[0][c] = G[c][c].x;
+  for (int q = tid; q < NP; q += ROT_THREADS) od[0][q] = G[tb_i[0][q]][tb_j[0][q]];
   __syncthreads();
   if (!any_flag) return;
   const double tol_in = 0.5 * a.tol, neg2 = a.neg2;
-  const int rounds = a.max_inner * (JP - 1);
-  int buf = 0;
-  int round = 0;
+  const int rounds = a.max_inner * n_in;
+  const bool g_waves = w < 4;          // wave-uniform role
+  const int t = tid & 255;
+  int buf = 0, round = 0;
   for (int R = 0; R < rounds; ++R) {
-    const int nround = round + 1 == JP - 1 ? 0 : round + 1;
-    const int pb = tid % NP;
+    const int nround = round + 1 == n_in ? 0 : round + 1;
+    const int pb = t % NP;
     const int ib = tb_i[round][pb], jb = tb_j[round][pb];
     const Rot rb = jac_rot(dd[buf][ib], dd[buf][jb], od[buf][pb], tol_in, neg2);
+    if (g_waves) {
 #pragma unroll
-    for (int k = 0; k < JOBS; ++k) {
-      const int pa = (tid + 256 * k) / NP;
-      const int ia = tb_i[round][pa], ja = tb_j[round][pa];
-      const Rot ra = jac_rot(dd[buf][ia], dd[buf][ja], od[buf][pa], tol_in, neg2);
-      double2 g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
-      rot_right(rb, g00, g01);
-      rot_right(rb, g10, g11);
-      rot_left(ra, g00, g10);
-      rot_left(ra, g01, g11);
-      G[ia][ib] = g00;
-      G[ia][jb] = g01;
-      G[ja][ib] = g10;
-      G[ja][jb] = g11;
-      double2 v0 = V[ia][ib], v1 = V[ia][jb];
-      rot_right(rb, v0, v1);
-      V[ia][ib] = v0;
-      V[ia][jb] = v1;
-      v0 = V[ja][ib];
-      v1 = V[ja][jb];
-      rot_right(rb, v0, v1);
-      V[ja][ib] = v0;
-      V[ja][jb] = v1;
-      // hand on the diagonal and the next round's pair entries
-      const int rows[2] = {ia, ja}, cols[2] = {ib, jb};
-      const int qr[2] = {tb_q[nround][ia], tb_q[nround][ja]};
-      const int qc[2] = {tb_q[nround][ib], tb_q[nround][jb]};
-      const double2 vals[2][2] = {{g00, g01}, {g10, g11}};
+      for (int k = 0; k < JOBS; ++k) {
+        const int pa = (t + 256 * k) / NP;
+        const int ia = tb_i[round][pa], ja = tb_j[round][pa];
+        const Rot ra = jac_rot(dd[buf][ia], dd[buf][ja], od[buf][pa], tol_in, neg2);
+        double2 g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
+        rot_right(rb, g00, g01);
+        rot_right(rb, g10, g11);
+        rot_left(ra, g00, g10);
+        rot_left(ra, g01, g11);
+        G[ia][ib] = g00;
+        G[ia][jb] = g01;
+        G[ja][ib] = g10;
+        G[ja][jb] = g11;
+        // hand on the diagonal and the next round's pair entries
+        const int rows[2] = {ia, ja}, cols[2] = {ib, jb};
+        const int qr[2] = {tb_q[nround][ia], tb_q[nround][ja]};
+        const int qc[2] = {tb_q[nround][ib], tb_q[nround][jb]};
+        const double2 vals[2][2] = {{g00, g01}, {g10, g11}};
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const int r = rows[x], c = cols[y];
-          if (r == c) dd[buf ^ 1][r] = vals[x][y].x;
-          else if (r < c && qr[x] == qc[y]) od[buf ^ 1][qr[x]] = vals[x][y];
-        }
+          for (int y = 0; y < 2; ++y) {
+            const int r = rows[x], c = cols[y];
+            if (r == c) dd[buf ^ 1][r] = vals[x][y].x;
+            else if (r < c && qr[x] == qc[y]) od[buf ^ 1][qr[x]] = vals[x][y];
+          }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < JOBS; ++k) {
+        const int pa = (t + 256 * k) / NP;
+        const int ia = tb_i[round][pa], ja = tb_j[round][pa];
+        double2 v0 = V[ia][ib], v1 = V[ia][jb], v2 = V[ja][ib], v3 = V[ja][jb];
+        rot_right(rb, v0, v1);
+        rot_right(rb, v2, v3);
+        V[ia][ib] = v0;
+        V[ia][jb] = v1;
+        V[ja][ib] = v2;
+        V[ja][jb] = v3;
+      }
     }
     buf ^= 1;
     round = nround;
@@ -363,11 +387,11 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
   const int rbeg = chunk * a.rows_per_chunk;
   const int rend = min(a.len, rbeg + a.rows_per_chunk);
   const int ntiles = (rend - rbeg + TR - 1) / TR;
-  constexpr int KS = JP / 4;
+  constexpr int KS = JP / 4, NW = ROT_THREADS / 64;
   double2 cur[KS], nxt[KS];
   const int m = lane & 15, ksub = lane >> 4;
-  auto load_tile_regs = [&](int t, double2 (&v)[KS]) {
-    const int row = rbeg + t * TR + m;
+  auto load_tile_regs = [&](int tt, double2 (&v)[KS]) {
+    const int row = rbeg + tt * TR + m;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int col = pair_col<JP>(4 * ks + ksub, bi, bj);
@@ -375,8 +399,8 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
     }
   };
   if (w < ntiles) load_tile_regs(w, cur);
-  for (int t = w; t < ntiles; t += 4) {
-    if (t + 4 < ntiles) load_tile_regs(t + 4, nxt);
+  for (int tt = w; tt < ntiles; tt += NW) {
+    if (tt + NW < ntiles) load_tile_regs(tt + NW, nxt);
     double4_t cr[NB], ci[NB];
 #pragma unroll
     for (int nt = 0; nt < NB; ++nt) {
@@ -396,7 +420,7 @@ __global__ __launch_bounds__(256) void k_jac_rotate(JacArgs a) {
         ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, v.x, ci[nt], 0, 0, 0);
       }
     }
-    const int row0 = rbeg + t * TR;
+    const int row0 = rbeg + tt * TR;
 #pragma unroll
     for (int nt = 0; nt < NB; ++nt)
 #pragma unroll
@@ -507,12 +531,17 @@ JacobiPlan jacobi_plan(int len, int cnt, int jb) {
   pl.n_chunks = std::max(1, std::min(target_chunks, max_chunks));
   pl.rows_per_chunk = (int)round_up(ceil_div(len, pl.n_chunks), TR);
   pl.n_chunks = ceil_div(len, pl.rows_per_chunk);
+  // the Gram pass is pure matrix-core streaming: twice the workgroups, so
+  // two share a compute unit and hide each other's load latency
+  pl.n_gchunks = std::max(1, std::min(2 * pl.n_chunks, max_chunks));
+  pl.rows_per_gchunk = (int)round_up(ceil_div(len, pl.n_gchunks), TR);
+  pl.n_gchunks = ceil_div(len, pl.rows_per_gchunk);
   return pl;
 }
 
 size_t jacobi_work_bytes(const JacobiPlan& pl) {
   const int JP = 2 * pl.jb;
-  return (size_t)pl.n_pairs * pl.n_chunks * JP * JP * sizeof(double2) + 2 * (size_t)pl.nbp * sizeof(int) +
+  return (size_t)pl.n_pairs * pl.n_gchunks * JP * JP * sizeof(double2) + 2 * (size_t)pl.nbp * sizeof(int) +
          256;
 }
 
@@ -530,17 +559,17 @@ static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bo
     {
       Probe pr(kKcJacGram, stream, fl, by);
       if (pl.jb == 16)
-        hipLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, a);
       else
-        hipLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, a);
     }
     HIP_LAUNCH_OK();
     {
       Probe pr(kKcJacRotate, stream, fl, 2.0 * by);
       if (pl.jb == 16)
-        hipLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, a);
       else
-        hipLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, a);
     }
     HIP_LAUNCH_OK();
   }
@@ -603,10 +632,12 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
   a.nbp = pl.nbp;
   a.rows_per_chunk = pl.rows_per_chunk;
   a.n_chunks = pl.n_chunks;
+  a.rows_per_gchunk = pl.rows_per_gchunk;
+  a.n_gchunks = pl.n_gchunks;
   a.round = 0;
   char* w = reinterpret_cast<char*>(work);
   a.part = reinterpret_cast<double2*>(w);
-  w += (size_t)pl.n_pairs * pl.n_chunks * (2 * pl.jb) * (2 * pl.jb) * sizeof(double2);
+  w += (size_t)pl.n_pairs * pl.n_gchunks * (2 * pl.jb) * (2 * pl.jb) * sizeof(double2);
   a.rot_prev = reinterpret_cast<int*>(w);
   a.rot_cur = a.rot_prev + pl.nbp;
   a.rot_count = rot_count_dev;
