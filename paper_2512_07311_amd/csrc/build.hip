@@ -16,6 +16,11 @@
 // orthogonality centre where the next update needs it.
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
@@ -598,12 +603,11 @@ int grid1d(int64_t n, int per = 256) {
 }
 
 static bool sort_columns_first() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("RCS_JACOBI_SORT");
-    v = (e && e[0] == '0') ? 0 : 1;
-  }
-  return v == 1;
+    return !(e && e[0] == '0');
+  }();
+  return v;
 }
 
 // Orthogonalise X (len x cnt) and produce Wn (k columns) and P (k x cnt).
@@ -930,8 +934,12 @@ static void apply_layer(rcs_state_s& st, const rcs_circuit_s& c, int layer) {
 }
 
 static void upload_gates_once() {
-  static bool done = false;
-  if (done) return;
+  static std::mutex mu;
+  static std::vector<int> done_devices;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(done_devices.begin(), done_devices.end(), dev) != done_devices.end()) return;
   double2 g[3][4];
   for (int i = 0; i < 3; ++i)
     for (int e = 0; e < 4; ++e) {
@@ -939,7 +947,7 @@ static void upload_gates_once() {
       g[i][e] = make_double2(v.real(), v.imag());
     }
   HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_gates1q), g, sizeof(g)));
-  done = true;
+  done_devices.push_back(dev);
 }
 
 void canonicalize(rcs_state_s& st, BuildWork& ws) {
@@ -1233,20 +1241,77 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
   RCS_API_BEGIN
   RCS_REQUIRE(circuits && chi && eps && out && n >= 0, "null argument");
   for (int i = 0; i < n; ++i) out[i] = nullptr;
-  rcs::BuildOptions b = to_options(opts);
-  std::vector<std::unique_ptr<rcs_state_s>> states;
-  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
   for (int i = 0; i < n; ++i) {
     RCS_REQUIRE(circuits[i], "null circuit in batch");
     RCS_REQUIRE(chi[i] >= 1 && chi[i] <= 2048, "chi must be in [1, 2048]");
     RCS_REQUIRE(eps[i] >= 0.0 && eps[i] < 1.0, "eps must be in [0, 1)");
-    auto st = std::make_unique<rcs_state_s>();
-    st->stream = rcs::as_stream(b.stream);
-    HIP_OK(hipGetDevice(&st->device));
-    rcs::state_alloc(*st, circuits[i]->n, chi[i]);
-    rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], b, *ws);
-    states.push_back(std::move(st));
   }
+  rcs::BuildOptions b = to_options(opts);
+  hipStream_t caller = rcs::as_stream(b.stream);
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  // Circuits are built concurrently by worker threads, each with its own
+  // stream and workspaces, taking circuits longest-first (cost ~ updates x
+  // bond cap^3): the latency-bound SVD sweeps of small bonds then overlap.
+  std::vector<int> order(n);
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    const double c = std::min<double>(chi[i], std::ldexp(1.0, circuits[i]->n / 2));
+    cost[i] = (double)circuits[i]->ops.size() * c * c * c;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  int n_workers = 8;
+  if (const char* e = std::getenv("RCS_BATCH_STREAMS")) n_workers = std::max(1, std::min(32, std::atoi(e)));
+  n_workers = std::max(1, std::min(n_workers, n));
+  hipEvent_t ready;
+  HIP_OK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIP_OK(hipEventRecord(ready, caller));
+  std::vector<std::unique_ptr<rcs_state_s>> states(n);
+  std::atomic<int> next{0};
+  std::atomic<bool> stop{false};
+  std::mutex err_mu;
+  rcs_status err_status = RCS_OK;
+  std::string err_msg;
+  auto worker = [&]() {
+    hipStream_t s = nullptr;
+    try {
+      HIP_OK(hipSetDevice(dev));
+      HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      HIP_OK(hipStreamWaitEvent(s, ready, 0));
+      std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+      rcs::BuildOptions bo = b;
+      bo.stream = s;
+      for (int j = next++; j < n && !stop; j = next++) {
+        const int i = order[j];
+        auto st = std::make_unique<rcs_state_s>();
+        st->stream = s;
+        st->device = dev;
+        rcs::state_alloc(*st, circuits[i]->n, chi[i]);
+        rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], bo, *ws);
+        HIP_OK(hipStreamSynchronize(s));
+        st->stream = caller;
+        states[i] = std::move(st);
+      }
+      HIP_OK(hipStreamSynchronize(s));
+    } catch (const rcs::Error& e) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (err_status == RCS_OK) {
+        err_status = e.status;
+        err_msg = e.what();
+      }
+      stop = true;
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 0; w < n_workers; ++w) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(ready);
+  if (err_status != RCS_OK) rcs::fail(err_status, err_msg);
   for (int i = 0; i < n; ++i) out[i] = states[i].release();
   RCS_API_END
 }

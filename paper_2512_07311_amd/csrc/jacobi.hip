@@ -452,12 +452,11 @@ __global__ void k_jac_roll(int* rot_prev, int* rot_cur, int* rot_count, int nbp,
 
 // ------------------------------------------------------------- driver
 static bool debug_jacobi() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("RCS_DEBUG_JACOBI");
-    v = (e && e[0] == '1') ? 1 : 0;
-  }
-  return v == 1;
+    return e && e[0] == '1';
+  }();
+  return v;
 }
 
 // Tuning table: buckets (cnt_max ascending) -> block width, inner sweeps.
@@ -576,12 +575,11 @@ static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bo
 }
 
 static bool use_graphs() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("RCS_JACOBI_GRAPH");
-    v = (e && e[0] == '1') ? 1 : 0;
-  }
-  return v == 1;
+    return e && e[0] == '1';
+  }();
+  return v;
 }
 
 // Cached executable graphs of one sweep (not the first), keyed by the plan

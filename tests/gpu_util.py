@@ -35,3 +35,21 @@ def compare_shots(gpu_bits, oracle_bits, tight):
     g = np.asarray(gpu_bits).astype(np.uint64)
     ok = (g == oracle_bits) | (tight >= 0)
     return bool(np.all(ok)), int(np.sum(tight >= 0)), int(np.sum(g != oracle_bits))
+
+
+def truncated_tolerance(om):
+    """Amplitude bar for a truncated fp64 build against the oracle.
+
+    A truncation keeps the span of the top-k singular vectors; a backward
+    error e in the two-site matrix rotates that span by about
+    e * s_k / (s_k - s_{k+1}) (first-order perturbation of singular
+    subspaces, Wedin 1972).  Both SVDs have e of order 1e-13 relative
+    (sqrt(m) u times the sweep count of a Jacobi or bidiagonal method), so the
+    bar is 1e-13 times the summed conditioning of the cuts, never below 1e-10.
+    """
+    kappa = 0.0
+    for rec in om.records:
+        s, k = rec["spectrum"], rec["k"]
+        if k < len(s) and s[k] > 1e-12 * s[0] and s[k - 1] > s[k]:
+            kappa += s[k - 1] / (s[k - 1] - s[k])
+    return max(1e-10, 1e-13 * kappa)

@@ -18,6 +18,10 @@ WORKLOADS = {
     "rcs53_6x9_c14_chi1024": dict(rows=6, cols=9, cycles=14, removed_random=1,
                                   chi=1024, eps=1e-8, shots=1_000_000,
                                   precision="split_bf16"),
+    # 64 independent circuits: n ~ U{20..40} on near-square grids, cycles ~
+    # U{8..20}, chi ~ U{64, 128, 256, 512} (batch seed 7), 50,000 shots each
+    "rcs_batch64_n20to40": dict(batch=64, batch_seed=7, n_lo=20, n_hi=40, cyc_lo=8, cyc_hi=20,
+                                chis=(64, 128, 256, 512), eps=1e-8, shots=50_000, precision="c64"),
     # 53 qubits, 20 cycles, chi cap 2048, 2.5M shots
     "rcs53_6x9_c20_chi2048": dict(rows=6, cols=9, cycles=20, removed_random=1,
                                   chi=2048, eps=1e-8, shots=2_500_000,

@@ -5,7 +5,7 @@ import pytest
 
 from oracle import circuit as oc, dense, mps, sample
 from tests import inputs
-from tests.gpu_util import get_rcs, to_complex, normwise_rel, oracle_state_from, compare_shots
+from tests.gpu_util import truncated_tolerance, get_rcs, to_complex, normwise_rel, oracle_state_from, compare_shots
 
 pytestmark = pytest.mark.gpu
 
@@ -13,24 +13,6 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def env():
     return get_rcs()
-
-
-def truncated_tolerance(om):
-    """Amplitude bar for a truncated fp64 build against the oracle.
-
-    A truncation keeps the span of the top-k singular vectors; a backward
-    error e in the two-site matrix rotates that span by about
-    e * s_k / (s_k - s_{k+1}) (first-order perturbation of singular
-    subspaces, Wedin 1972).  Both SVDs have e of order 1e-13 relative
-    (sqrt(m) u times the sweep count of a Jacobi or bidiagonal method), so the
-    bar is 1e-13 times the summed conditioning of the cuts, never below 1e-10.
-    """
-    kappa = 0.0
-    for rec in om.records:
-        s, k = rec["spectrum"], rec["k"]
-        if k < len(s) and s[k] > 1e-12 * s[0] and s[k - 1] > s[k]:
-            kappa += s[k - 1] / (s[k - 1] - s[k])
-    return max(1e-10, 1e-13 * kappa)
 
 
 def _amps(torch, g, b):
