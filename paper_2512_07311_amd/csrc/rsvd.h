@@ -5,10 +5,13 @@
 
 namespace rcs {
 
+constexpr int kMaxKChunks = 16;   // row chunks of the Gram-Schmidt projections
+
 struct RsvdWork {
-  DevBuf bufQ, bufZ, bufC, bufG, bufR;
-  double2 *Q = nullptr, *Z = nullptr, *C = nullptr, *gpart = nullptr, *Rinv = nullptr;
-  int ldq = 0, ldz = 0;
+  DevBuf bufQ, bufZ, bufC, bufCp, bufPp, bufG, bufR;
+  double2 *Q = nullptr, *Z = nullptr, *C = nullptr, *Cpart = nullptr, *Ppart = nullptr, *gpart = nullptr,
+          *Rinv = nullptr;
+  int ldq = 0, ldz = 0, ldc = 0;
 };
 
 void rsvd_work_ensure(RsvdWork& w, int len, int cnt, int l);

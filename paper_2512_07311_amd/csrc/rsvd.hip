@@ -75,46 +75,81 @@ __global__ __launch_bounds__(256) void k_mhq32(const double2* M, int ldx, int le
   });
 }
 
-// C (j0 x pw, row-major ld 64) = Q[:, :j0]^H Y[:, j0:j0+pw]   (fp64)
+// Partial C (j0 x pw, row-major ld 64) = Q[r0:r0+K, :j0]^H Y[r0:r0+K, j0:j0+pw]
+// over the row chunk blockIdx.x (fp64); summed in fixed order by k_csum.
 __global__ __launch_bounds__(GT_THREADS) void k_qhy(const double2* Q, int ldq, int len, int j0, int pw,
-                                                   double2* C) {
+                                                   int rows_kc, int ldc, double2* Cpart) {
   __shared__ SmemC64 sm;
-  const int m0 = blockIdx.y * GT_M;
+  const int m0 = blockIdx.y * GT_M, kc = blockIdx.x;
+  const int r0 = kc * rows_kc;
+  const int K = min(rows_kc, len - r0);
   auto fa = [&](int m, int k) -> double2 {
-    const double2 v = Q[(int64_t)m * ldq + k];
+    const double2 v = Q[(int64_t)m * ldq + r0 + k];
     return make_double2(v.x, -v.y);
   };
-  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)(j0 + n) * ldq + k]; };
-  LoadA<decltype(fa), true> la{fa, m0, j0, len};
-  LoadB<decltype(fb), false> lb{fb, 0, len, pw};
+  auto fb = [&](int k, int n) -> double2 { return Q[(int64_t)(j0 + n) * ldq + r0 + k]; };
+  LoadA<decltype(fa), true> la{fa, m0, j0, K};
+  LoadB<decltype(fb), false> lb{fb, 0, K, pw};
   AccC64 acc;
   acc_zero(acc);
-  cgemm_mainloop(la, lb, len, sm, acc);
+  cgemm_mainloop(la, lb, K, sm, acc);
+  double2* C = Cpart + (int64_t)kc * ldc * 64;
   acc_foreach(acc, [&](int r, int c, double re, double im) {
     const int m = m0 + r;
     if (m < j0 && c < pw) C[(int64_t)m * 64 + c] = make_double2(re, im);
   });
 }
 
-// Y[:, j0:j0+pw] -= Q[:, :j0] C   (in place by row tiles)
-__global__ __launch_bounds__(GT_THREADS) void k_ysub(double2* Q, int ldq, int len, int j0, int pw,
-                                                    const double2* C) {
+// C[m][c] = sum over row chunks of the partials, in chunk order.
+__global__ void k_csum(const double2* Cpart, int n_kc, int ldc, int j0, double2* C) {
+  const int64_t tot = (int64_t)j0 * 64;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int kc = 0; kc < n_kc; ++kc) {
+      const double2 v = Cpart[(int64_t)kc * ldc * 64 + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    C[e] = acc;
+  }
+}
+
+// Partial P_kc (len x pw, col-major ld ldq) = Q[:, K-chunk kc] C[K-chunk kc, :]
+// over the column chunk blockIdx.x of Q[:, :j0].
+__global__ __launch_bounds__(GT_THREADS) void k_ysub(const double2* Q, int ldq, int len, int j0, int pw,
+                                                    const double2* C, int cols_kc, double2* Ppart) {
   __shared__ SmemC64 sm;
-  const int m0 = blockIdx.y * GT_M;
-  auto fa = [&](int m, int k) -> double2 { return Q[(int64_t)k * ldq + m]; };
-  auto fb = [&](int k, int n) -> double2 { return C[(int64_t)k * 64 + n]; };
-  LoadA<decltype(fa), false> la{fa, m0, len, j0};
-  LoadB<decltype(fb), true> lb{fb, 0, j0, pw};
+  const int m0 = blockIdx.y * GT_M, kc = blockIdx.x;
+  const int c0 = kc * cols_kc;
+  const int K = min(cols_kc, j0 - c0);
+  auto fa = [&](int m, int k) -> double2 { return Q[(int64_t)(c0 + k) * ldq + m]; };
+  auto fb = [&](int k, int n) -> double2 { return C[(int64_t)(c0 + k) * 64 + n]; };
+  LoadA<decltype(fa), false> la{fa, m0, len, K};
+  LoadB<decltype(fb), true> lb{fb, 0, K, pw};
   AccC64 acc;
   acc_zero(acc);
-  cgemm_mainloop(la, lb, j0, sm, acc);
+  cgemm_mainloop(la, lb, K, sm, acc);
+  double2* P = Ppart + (int64_t)kc * 64 * ldq;
   acc_foreach(acc, [&](int r, int c, double re, double im) {
     const int m = m0 + r;
-    if (m < len && c < pw) {
-      double2* y = Q + (int64_t)(j0 + c) * ldq + m;
-      *y = make_double2(y->x - re, y->y - im);
-    }
+    if (m < len && c < pw) P[(int64_t)c * ldq + m] = make_double2(re, im);
   });
+}
+
+// Y[:, j0:j0+pw] -= sum over column chunks of the partials, in chunk order.
+__global__ void k_ysub_apply(double2* Y, int ldq, int len, int j0, int pw, const double2* Ppart, int n_kc) {
+  const int64_t tot = (int64_t)pw * len;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / len), m = (int)(e % len);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int kc = 0; kc < n_kc; ++kc) {
+      const double2 v = Ppart[(int64_t)kc * 64 * ldq + (int64_t)c * ldq + m];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    double2* y = Y + (int64_t)(j0 + c) * ldq + m;
+    *y = make_double2(y->x - acc.x, y->y - acc.y);
+  }
 }
 
 // G (64 x 64) = Yp^H Yp for the panel (partial over row chunks, summed in
@@ -142,6 +177,10 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_gram(const double2* Q, int
 // Cholesky G = R^H R (R upper triangular) with pivot guard, then Rinv = R^-1.
 // A pivot below guard * max(diag) marks the column dependent: its row of R
 // is set to zero and its column of Rinv to zero, so the panel column becomes 0.
+// Right-looking, one barrier per step: the trailing update of step k uses
+// the unscaled row k and its pivot d (R_ij -= conj(R_ki) R_kj / d), and row k
+// is scaled afterwards, while step k+1 touches only rows > k.  The inverse
+// solves R Rinv = I bottom-up, one row per step, four lanes per column.
 __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chunks, int pw, double guard,
                                                  double2* Rinv) {
   __shared__ double2 R[64][65];
@@ -168,58 +207,58 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
     dmax = m;
   }
   __syncthreads();
-  // right-looking Cholesky on the upper triangle: R[k][j] for j >= k
+  const int ty = tid >> 4, tx = tid & 15;
   for (int k = 0; k < pw; ++k) {
-    __shared__ double piv;
-    if (tid == 0) {
-      const double d = R[k][k].x;
-      if (!(d > guard * dmax) || dead[k]) {
-        dead[k] = 1;
-        piv = 0.0;
-      } else {
-        piv = sqrt(d);
-      }
-    }
-    __syncthreads();
-    const double p = piv;
-    // row k: R[k][j] /= p  (j > k), R[k][k] = p
-    if (tid < 64) {
-      const int j = tid;
-      if (j > k) R[k][j] = p > 0.0 ? make_double2(R[k][j].x / p, R[k][j].y / p) : make_double2(0.0, 0.0);
-      if (j == k) R[k][k] = make_double2(p, 0.0);
-    }
-    __syncthreads();
-    // trailing update: R[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e / 64, j = e % 64;
-      if (i > k && j >= i && j < pw) {
-        const double2 a = R[k][i], b = R[k][j];
-        R[i][j] = make_double2(R[i][j].x - (a.x * b.x + a.y * b.y), R[i][j].y - (a.x * b.y - a.y * b.x));
-      }
-    }
-    __syncthreads();
-  }
-  // Rinv column by column: R Rinv[:, c] = e_c, back substitution
-  if (tid < 64) {
-    const int c = tid;
-    if (c < pw && !dead[c]) {
-      for (int i = c; i >= 0; --i) {
-        if (dead[i]) {
-          Ri[i][c] = make_double2(0.0, 0.0);
-          continue;
+    const double d = R[k][k].x;
+    const bool dk = !(d > guard * dmax) || dead[k];
+    if (!dk) {
+      const double rd = 1.0 / d;
+      for (int i = k + 1 + ty; i < pw; i += 16) {
+        const double2 a = R[k][i];
+        for (int j = k + 1 + tx; j < pw; j += 16) {
+          if (j >= i) {
+            const double2 b = R[k][j];
+            const double re = (a.x * b.x + a.y * b.y) * rd, im = (a.x * b.y - a.y * b.x) * rd;
+            R[i][j] = make_double2(R[i][j].x - re, R[i][j].y - im);
+          }
         }
-        double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
-        for (int j = i + 1; j <= c; ++j) {
-          const double2 a = R[i][j], b = Ri[j][c];
-          s.x -= a.x * b.x - a.y * b.y;
-          s.y -= a.x * b.y + a.y * b.x;
-        }
-        const double d = R[i][i].x;
-        Ri[i][c] = make_double2(s.x / d, s.y / d);
       }
+    }
+    __syncthreads();
+    const double p = dk ? 0.0 : sqrt(d);
+    const double rp = dk ? 0.0 : 1.0 / p;
+    if (tid > k && tid < pw) R[k][tid] = make_double2(R[k][tid].x * rp, R[k][tid].y * rp);
+    if (tid == k) {
+      R[k][k] = make_double2(p, 0.0);
+      dead[k] = dk ? 1 : 0;
     }
   }
   __syncthreads();
+  // Rinv: row i = (e_i - sum_{j>i} R[i][j] Rinv[j][:]) / R[i][i], bottom-up
+  const int c = tid >> 2, part4 = tid & 3;
+  for (int i = pw - 1; i >= 0; --i) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (c < pw && c >= i) {
+      for (int j = i + 1 + part4; j <= c; j += 4) {
+        const double2 a = R[i][j], b = Ri[j][c];
+        acc.x += a.x * b.x - a.y * b.y;
+        acc.y += a.x * b.y + a.y * b.x;
+      }
+    }
+    acc.x += __shfl_xor(acc.x, 1);
+    acc.y += __shfl_xor(acc.y, 1);
+    acc.x += __shfl_xor(acc.x, 2);
+    acc.y += __shfl_xor(acc.y, 2);
+    if (part4 == 0 && c < pw && c >= i) {
+      if (dead[i] || dead[c]) {
+        Ri[i][c] = make_double2(0.0, 0.0);
+      } else {
+        const double rd = 1.0 / R[i][i].x;
+        Ri[i][c] = make_double2(((i == c ? 1.0 : 0.0) - acc.x) * rd, -acc.y * rd);
+      }
+    }
+    __syncthreads();
+  }
   for (int e = tid; e < 64 * 64; e += 256) Rinv[e] = Ri[e / 64][e % 64];
 }
 
@@ -243,15 +282,32 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_apply(double2* Q, int ldq,
 
 // Orthonormalise the l columns of Y (len x l, col-major, ld ldq) in place.
 static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s) {
-  const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 64)), 64);
+  // at most 8 row chunks: the single-workgroup Cholesky sums the partials
+  const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 8)), 64);
   const int n_chunks = ceil_div(len, rows_per_chunk);
   for (int j0 = 0; j0 < l; j0 += 64) {
     const int pw = std::min(64, l - j0);
     if (j0 > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_qhy, dim3(1, ceil_div(j0, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, w.C);
+        // split the length-len reduction over row chunks so ~256 workgroups run
+        const int ny = ceil_div(j0, GT_M);
+        const int n_kc = std::max(1, std::min({kMaxKChunks, 256 / ny, ceil_div(len, 128)}));
+        const int rows_kc = (int)round_up(ceil_div(len, n_kc), 16);
+        const int nk = ceil_div(len, rows_kc);
+        hipLaunchKernelGGL(k_qhy, dim3(nk, ny), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, rows_kc, w.ldc,
+                           w.Cpart);
         HIP_LAUNCH_OK();
-        hipLaunchKernelGGL(k_ysub, dim3(1, ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, w.C);
+        hipLaunchKernelGGL(k_csum, dim3(ceil_div(j0 * 64, 256)), dim3(256), 0, s, w.Cpart, nk, w.ldc, j0, w.C);
+        HIP_LAUNCH_OK();
+        const int nm = ceil_div(len, GT_M);
+        const int n_pc = std::max(1, std::min({kMaxKChunks, 256 / nm, ceil_div(j0, 64)}));
+        const int cols_kc = (int)round_up(ceil_div(j0, n_pc), 16);
+        const int np = ceil_div(j0, cols_kc);
+        hipLaunchKernelGGL(k_ysub, dim3(np, nm), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, w.C, cols_kc,
+                           w.Ppart);
+        HIP_LAUNCH_OK();
+        hipLaunchKernelGGL(k_ysub_apply, dim3(ceil_div(pw * len, 256)), dim3(256), 0, s, Y, ldq, len, j0, pw, w.Ppart,
+                           np);
         HIP_LAUNCH_OK();
       }
     }
@@ -273,6 +329,11 @@ void rsvd_work_ensure(RsvdWork& w, int len, int cnt, int l) {
   w.bufQ.ensure((size_t)ldq * round_up(l, 64) * sizeof(double2));
   w.bufZ.ensure((size_t)ldz * round_up(l, 64) * sizeof(double2));
   w.bufC.ensure((size_t)round_up(l, 64) * 64 * sizeof(double2));
+  w.ldc = (int)round_up(l, 64);
+  w.bufCp.ensure((size_t)kMaxKChunks * w.ldc * 64 * sizeof(double2));
+  w.Cpart = w.bufCp.as<double2>();
+  w.bufPp.ensure((size_t)kMaxKChunks * 64 * std::max(ldq, ldz) * sizeof(double2));
+  w.Ppart = w.bufPp.as<double2>();
   const int mx = std::max(len, cnt);
   const int n_chunks = ceil_div(mx, (int)round_up(std::max(64, ceil_div(mx, 64)), 64)) + 1;
   w.bufG.ensure((size_t)n_chunks * 4096 * sizeof(double2));
