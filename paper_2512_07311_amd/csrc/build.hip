@@ -616,9 +616,14 @@ struct SplitResult {
   double eps_step, w, nrm;
 };
 
+// ortho_only: the caller needs an exact factorisation X = Q P with Q
+// orthonormal, not singular vectors (centre moves): the Jacobi iteration
+// stops at a loose orthogonality (relative 1e-7) and two Newton-Schulz steps
+// (error e -> ~3e^2/4 each, from e <= k 1e-7) make the kept columns
+// orthonormal to fp64 rounding; P = Q^H X is then exact.
 static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl, int cap,
                              double eps, bool renorm, std::vector<double>* spectrum_out,
-                             const double* extra_dev = nullptr) {
+                             const double* extra_dev = nullptr, bool ortho_only = false) {
   hipStream_t s = st.stream;
   double2* X = ws.X.as<double2>();
   // ||X||_F^2 scales the Jacobi's numerically-zero column threshold
@@ -639,7 +644,7 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
                        pl.ldx, pl.len, ws.order.as<int>(), X);
     HIP_LAUNCH_OK();
   }
-  int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
+  int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60, ortho_only ? 1e-7 : 0.0);
   st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
   hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
@@ -661,14 +666,20 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(pl.ldx, 256), out.k), dim3(256), 0, s, X, pl.ldx,
                      ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
   HIP_LAUNCH_OK();
-  // orthonormalise: X <- Wn (3I - Wn^H Wn)/2 (X is free after the gather)
-  hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(out.k, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
-                     ws.Wn.as<double2>(), pl.ldx, pl.len, out.k, ws.H.as<double2>());
-  HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(out.k, GT_N), ceil_div(pl.len, GT_M)), dim3(GT_THREADS), 0, s,
-                     ws.Wn.as<double2>(), pl.ldx, pl.len, out.k, ws.H.as<double2>(), X);
-  HIP_LAUNCH_OK();
-  ws.wn_final = X;
+  // orthonormalise: X <- Wn (3I - Wn^H Wn)/2 (X is free after the gather);
+  // a second step, from X back into Wn, after a loose Jacobi iteration
+  double2* src = ws.Wn.as<double2>();
+  double2* dst = X;
+  for (int it = 0; it < (ortho_only ? 2 : 1); ++it) {
+    hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(out.k, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s, src,
+                       pl.ldx, pl.len, out.k, ws.H.as<double2>());
+    HIP_LAUNCH_OK();
+    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(out.k, GT_N), ceil_div(pl.len, GT_M)), dim3(GT_THREADS), 0, s,
+                       src, pl.ldx, pl.len, out.k, ws.H.as<double2>(), dst);
+    HIP_LAUNCH_OK();
+    std::swap(src, dst);
+  }
+  ws.wn_final = src;
   const double scale = renorm ? 1.0 / out.nrm : 1.0;
   hipLaunchKernelGGL(k_project, dim3(ceil_div(pl.cnt, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
                      ws.wn_final, ws.X0.as<double2>(), pl.ldx, pl.len, out.k, pl.cnt, scale,
@@ -708,7 +719,7 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   hipLaunchKernelGGL(k_load_site, dim3(grid1d((int64_t)2 * dl * dr)), dim3(256), 0, s, st.site[c], dl, dr,
                      right ? 1 : 0, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
   HIP_LAUNCH_OK();
-  SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr);
+  SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr, nullptr, true);
   const int k = r.k;
   hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
                      ws.wn_final, pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);

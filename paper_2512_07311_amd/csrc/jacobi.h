@@ -24,7 +24,8 @@ void jacobi_init_attributes();
 // Orthogonalises the columns of x in place; returns the number of sweeps
 // (the last one rotates nothing).  fro2 = ||x||_F^2; columns below
 // 8 u sqrt(len) ||x||_F count as numerically zero.
+// tol > 0 replaces the default relative orthogonality tolerance 16 u sqrt(len).
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
-               int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps);
+               int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol = 0.0);
 
 }  // namespace rcs

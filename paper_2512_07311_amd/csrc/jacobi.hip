@@ -622,7 +622,7 @@ static hipGraphExec_t sweep_graph(const JacobiPlan& pl, const JacArgs& a, void* 
 }
 
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev, int* rot_count_host,
-               double fro2, hipStream_t stream, int max_sweeps) {
+               double fro2, hipStream_t stream, int max_sweeps, double tol) {
   JacArgs a;
   a.x = x;
   a.ldx = pl.ldx;
@@ -639,7 +639,7 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
   a.rot_prev = reinterpret_cast<int*>(w);
   a.rot_cur = a.rot_prev + pl.nbp;
   a.rot_count = rot_count_dev;
-  a.tol = 16.0 * 1.11e-16 * std::sqrt((double)std::max(pl.len, 16));
+  a.tol = tol > 0.0 ? tol : 16.0 * 1.11e-16 * std::sqrt((double)std::max(pl.len, 16));
   // columns shorter than delta ||X||_F (delta = 8 u sqrt(len)) are numerically
   // zero: below the absolute accuracy of any fp64 SVD, and they must not be
   // required to be mutually orthogonal (a wide matrix has more columns than
