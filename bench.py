@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-ops", type=int, default=-1, help="truncate the schedule (debugging only)")
+    ap.add_argument("--hbm-copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 8 device-to-device copies of MIB MiB (scales rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -157,6 +159,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.hbm_copy_calibration:
+        # a plain copy of known size: each launch reads and writes MIB MiB
+        torch.cuda.set_device(0)
+        n = args.hbm_copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(8):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"hbm_copy_calibration_mib": args.hbm_copy_calibration, "launches": 8}), flush=True)
+        return
     import paper_2512_07311_amd as rcs
     from tests import inputs
     torch.cuda.set_device(0)
@@ -238,6 +251,8 @@ def main():
         "roofline": roof,
         "kernels": {q["name"]: {"launches": q["launches"], "timed": q["timed"],
                                 "avg_us": 1e6 * q["seconds"] / max(q["timed"], 1),
+                                "flop_per_launch": q["flops"] / max(q["timed"], 1),
+                                "bytes_per_launch": q["bytes"] / max(q["timed"], 1),
                                 "est_total_s": e} for q, e in zip(prof, est)},
     }
     if not args.no_cpu_baseline:
