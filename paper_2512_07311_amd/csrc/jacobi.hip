@@ -217,17 +217,21 @@ __device__ inline Rot jac_rot(double gii, double gjj, double2 g, double tol, dou
   return r;
 }
 
-// With a = s e:
+// With a = s e (precomputed once per rotation: RotA = {c, Re a, Im a}):
 // right action (X J):  x_i' = c x_i - conj(a) x_j,  x_j' = a x_i + c x_j;
 // left action (J^H X): x_i' = c x_i - a x_j,        x_j' = conj(a) x_i + c x_j.
-__device__ inline void rot_right(const Rot& r, double2& xi, double2& xj) {
-  const double ax = r.s * r.ex, ay = r.s * r.ey;
+struct RotA {
+  double c, ax, ay;
+};
+__device__ inline RotA rot_a(const Rot& r) { return RotA{r.c, r.s * r.ex, r.s * r.ey}; }
+__device__ inline void rot_right(const RotA& r, double2& xi, double2& xj) {
+  const double ax = r.ax, ay = r.ay;
   const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, ay * xj.y)), fma(r.c, xi.y, fma(ay, xj.x, -ax * xj.y)));
   xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, -ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, ay * xi.x)));
   xi = ni;
 }
-__device__ inline void rot_left(const Rot& r, double2& xi, double2& xj) {
-  const double ax = r.s * r.ex, ay = r.s * r.ey;
+__device__ inline void rot_left(const RotA& r, double2& xi, double2& xj) {
+  const double ax = r.ax, ay = r.ay;
   const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, -ay * xj.y)), fma(r.c, xi.y, -fma(ax, xj.y, ay * xj.x)));
   xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, -ay * xi.x)));
   xi = ni;
@@ -253,12 +257,13 @@ __device__ inline int rr_pair_of(int c, int round) {
 // same unitary V_p), and rotate this chunk's rows, Y_p <- Y_p V_p, on the
 // matrix cores.
 //
-// Inner solve: a round applies JP/2 disjoint rotations at once.  Waves 0-3
-// take the (JP/2)^2 blocks G[pair a, pair b] <- J_a^H G[a, b] J_b, waves 4-7
-// the blocks V[rows of a, pair b] <- V J_b (one of each per SIMD, so their
-// latencies overlap), all in place: each entry belongs to one job per
-// round.  The diagonal and the next round's pair entries are handed on
-// through small double-buffered arrays, so a round needs one barrier.
+// Inner solve: a round applies JP/2 disjoint rotations at once.  JP/2 lanes
+// compute the round's rotations into LDS; then waves 0-3 take the (JP/2)^2
+// blocks G[pair a, pair b] <- J_a^H G[a, b] J_b and waves 4-7 the blocks
+// V[rows of a, pair b] <- V J_b (one of each per SIMD, so their latencies
+// overlap), all in place: each entry belongs to one job per round.  The
+// diagonal and the next round's pair entries are handed on through small
+// double-buffered arrays.
 constexpr int ROT_THREADS = 512;
 template <int JP>
 __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
@@ -269,6 +274,7 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   __shared__ double dd[2][JP];
   __shared__ double2 od[2][NP];
   __shared__ unsigned char tb_i[JP - 1][NP], tb_j[JP - 1][NP], tb_q[JP - 1][JP];
+  __shared__ RotA rp[NP];
   __shared__ int any_flag;
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
@@ -332,15 +338,21 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   int buf = 0, round = 0;
   for (int R = 0; R < rounds; ++R) {
     const int nround = round + 1 == n_in ? 0 : round + 1;
+    // the round's rotations, once each
+    if (tid < NP) {
+      const int i = tb_i[round][tid], j = tb_j[round][tid];
+      rp[tid] = rot_a(jac_rot(dd[buf][i], dd[buf][j], od[buf][tid], tol_in, neg2));
+    }
+    __syncthreads();
     const int pb = t % NP;
     const int ib = tb_i[round][pb], jb = tb_j[round][pb];
-    const Rot rb = jac_rot(dd[buf][ib], dd[buf][jb], od[buf][pb], tol_in, neg2);
+    const RotA rb = rp[pb];
     if (g_waves) {
 #pragma unroll
       for (int k = 0; k < JOBS; ++k) {
         const int pa = (t + 256 * k) / NP;
         const int ia = tb_i[round][pa], ja = tb_j[round][pa];
-        const Rot ra = jac_rot(dd[buf][ia], dd[buf][ja], od[buf][pa], tol_in, neg2);
+        const RotA ra = rp[pa];
         double2 g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
         rot_right(rb, g00, g01);
         rot_right(rb, g10, g11);
@@ -351,18 +363,16 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
         G[ja][ib] = g10;
         G[ja][jb] = g11;
         // hand on the diagonal and the next round's pair entries
-        const int rows[2] = {ia, ja}, cols[2] = {ib, jb};
-        const int qr[2] = {tb_q[nround][ia], tb_q[nround][ja]};
-        const int qc[2] = {tb_q[nround][ib], tb_q[nround][jb]};
-        const double2 vals[2][2] = {{g00, g01}, {g10, g11}};
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            const int r = rows[x], c = cols[y];
-            if (r == c) dd[buf ^ 1][r] = vals[x][y].x;
-            else if (r < c && qr[x] == qc[y]) od[buf ^ 1][qr[x]] = vals[x][y];
-          }
+        if (pa == pb) {
+          dd[buf ^ 1][ia] = g00.x;
+          dd[buf ^ 1][ja] = g11.x;
+        }
+        const int qa = tb_q[nround][ia], qa2 = tb_q[nround][ja];
+        const int qb = tb_q[nround][ib], qb2 = tb_q[nround][jb];
+        if (ia < ib && qa == qb) od[buf ^ 1][qa] = g00;
+        if (ia < jb && qa == qb2) od[buf ^ 1][qa] = g01;
+        if (ja < ib && qa2 == qb) od[buf ^ 1][qa2] = g10;
+        if (ja < jb && qa2 == qb2) od[buf ^ 1][qa2] = g11;
       }
     } else {
 #pragma unroll
