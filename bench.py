@@ -120,7 +120,9 @@ def main_batch(args, wl):
     import numpy as np
     import torch
     import paper_2512_07311_amd as rcs
+    from paper_2512_07311_amd import autotune
     torch.cuda.set_device(0)
+    tuned = os.path.exists(autotune.TUNING_FILE) and autotune.load(autotune.TUNING_FILE, torch)
     specs, step = batch_step_fn(rcs, torch, wl, args)
     for _ in range(args.warmup):
         step()
@@ -139,7 +141,8 @@ def main_batch(args, wl):
         "dtype": "c64/f64", "data": "synthetic (seeded random circuits)",
         "config": {"workload": args.workload, "circuits": len(states), "shots_per_circuit": shots // len(states),
                    "qubits": [s["n"] for s in specs], "cycles": [s["cycles"] for s in specs],
-                   "chi": [s["chi"] for s in specs], "eps": wl["eps"], "contraction": wl["precision"]},
+                   "chi": [s["chi"] for s in specs], "eps": wl["eps"], "contraction": wl["precision"],
+                   "autotuned": bool(tuned)},
         "state_build_s": t_build, "sample_s": t_sample,
         "self_xeb_mean": float(np.mean(xs)), "log_fidelity_est": [i.log_fidelity_est for i in infos],
     }

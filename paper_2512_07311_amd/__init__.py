@@ -15,6 +15,12 @@ LIB_PATH = os.path.join(_HERE, "librcs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError("librcs.so is not built (run __graft_entry__.build() or "
                       "python paper_2512_07311_amd/build_lib.py)")
+# torch ships its own HIP runtime; loading it first makes librcs bind to the
+# same runtime (two runtimes in one process do not share devices or streams)
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:
+    _torch = None
 _lib = C.CDLL(LIB_PATH)
 
 RCS_PREC_C128, RCS_PREC_C64, RCS_PREC_SPLIT_BF16 = 0, 1, 2

@@ -4,6 +4,9 @@ sweeps) per column-count bucket, timed on the device through the C ABI.
 The cache is a JSON file keyed by the GPU architecture name:
   {"gfx950": [{"cnt_max": 128, "block": 16, "inner": 1, "seconds": ...}, ...]}
 `load()` registers a cached table with the library (rcs_tuning_set).
+`python -m paper_2512_07311_amd.autotune OUT.json` tunes on the current GPU
+and writes the table; `TUNING_FILE` (next to this module) is the table the
+benchmark loads when it exists.
 """
 import json
 import os
@@ -14,6 +17,7 @@ import numpy as np
 import paper_2512_07311_amd as rcs
 
 BUCKETS = (64, 128, 256, 512, 1024, 2048, 4096)
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 CANDIDATES = [(16, 1), (16, 2), (32, 1), (32, 2)]
 
 
@@ -75,3 +79,13 @@ def load(path, torch):
     for e in table:
         rcs.tuning_set(e["cnt_max"], e["block"], e["inner"])
     return True
+
+
+if __name__ == "__main__":
+    import sys
+    import torch
+    out = sys.argv[1] if len(sys.argv) > 1 else TUNING_FILE
+    table = tune(torch)
+    save(out, table, torch)
+    for e in table:
+        print(json.dumps(e), flush=True)
