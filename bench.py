@@ -46,6 +46,35 @@ def parse():
     return ap.parse_args()
 
 
+# the source file of each probed kernel class (its hash ties counter data to
+# the kernel version it was taken on)
+KERNEL_SOURCE = {"k_chain_gemm": "sample.hip", "k_jac_gram": "jacobi.hip", "k_jac_rotate": "jacobi.hip",
+                 "k_two_site": "build.hip", "k_range_finder": "rsvd.hip"}
+
+
+def source_hash(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2512_07311_amd", "csrc", KERNEL_SOURCE[kernel])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, form):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (FETCH_SIZE and WRITE_SIZE runs of this workload, calibrated by a
+    copy kernel), or None when there are none for the current kernel source."""
+    import glob
+    want = {"kernel": kernel, "workload": workload, "form": form, "source_sha": source_hash(kernel)}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic-json: "):
+                    d = json.loads(line[len("traffic-json: "):])
+                    if all(d.get(k) == v for k, v in want.items()):
+                        return d["bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(wl, seed, budget_s=20.0):
     """The oracle (numpy fp64) timed on a bounded sample of the same workload
     and scaled to end-to-end shots/s for the full schedule and shot count:
@@ -233,12 +262,23 @@ def main():
     p = prof[dom]
     dt = {0: "fp64", 1: "fp64", 2: "fp64", 3: {"c128": "fp64", "c64": "fp32", "split_bf16": "bf16"}.get(
         kw["contraction"], "fp64"), 4: "fp32"}[dom]
-    achieved = p["flops"] / p["seconds"] if p["seconds"] > 0 else 0.0
-    roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[dt] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAKS[dt], "traffic": None, "kernel": p["name"],
+    # the roof is set by the kernel's algorithmic intensity against the ridge
+    # point of its datatype: below it the kernel is bound by HBM bandwidth
+    intensity = p["flops"] / max(p["bytes"], 1.0)
+    if intensity < PEAKS[dt] / PEAKS["hbm"]:
+        achieved = p["bytes"] / p["seconds"] if p["seconds"] > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAKS["hbm"]}
+    else:
+        achieved = p["flops"] / p["seconds"] if p["seconds"] > 0 else 0.0
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[dt] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAKS[dt]}
+    roof.update({"traffic": measured_traffic(p["name"], args.workload, args.form),
+            "intensity_flop_per_byte": intensity, "dtype": dt,
+            "kernel": p["name"], "kernel_source_sha": source_hash(p["name"]),
             "avg_launch_us": 1e6 * p["seconds"] / max(p["timed"], 1),
             "launches_per_step": p["launches"] // max(args.steps, 1),
-            "kernel_share_of_step": est[dom] / max(t1 - t0, 1e-9)}
+            "kernel_share_of_step": est[dom] / max(t1 - t0, 1e-9)})
     out = {
         "metric": "state-build s + shots/s per MI355X at chi=1024, learned/FP32 vs plain FP64, XEB",
         "value": shots / sec, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
