@@ -277,12 +277,17 @@ rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float
 
 /* ------------------------------------------------------------ measurement
  * Sampled kernel timing for roofline reporting.  With every > 0, every
- * every-th launch of each timed kernel class is bracketed by HIP events on
- * the stream it runs on, together with the algorithmic flops and HBM bytes
- * of that launch; every = 0 disables probing.  Both calls clear the
- * counters.  Classes: 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram,
- * 2 Jacobi rotation, 3 two-site contraction, 4 randomized range finder. */
+ * every-th launch of each timed kernel class is timed by start/stop events
+ * attached to the launch (hipExtLaunchKernelGGL) on the stream it runs on,
+ * together with the algorithmic flops and HBM bytes of that launch;
+ * every = 0 disables probing.  Both calls clear the counters.  Classes:
+ * 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram, 2 Jacobi rotation,
+ * 3 two-site contraction, 4 randomized range finder. */
 rcs_status rcs_profile_enable(int32_t every);
+/* Mean event interval (seconds, host output) of 32 back-to-back launches of
+ * an empty one-workgroup kernel on the null stream, timed the same way: the
+ * floor of any probed launch time (dispatch and event overhead). */
+rcs_status rcs_profile_event_floor(double* seconds);
 /* Per class: launches seen, launches timed, summed seconds / flops / bytes of
  * the timed launches.  Synchronises the pending events. */
 rcs_status rcs_profile_read(int32_t kclass, int64_t* launches, int64_t* timed, double* seconds,

@@ -95,6 +95,7 @@ _SIGS = {
     "rcs_mlp_forward": [_vp, _vp, _i32, _vp, _vp],
     "rcs_mlp_backward": [_vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "rcs_profile_enable": [_i32],
+    "rcs_profile_event_floor": [_P(_d)],
     "rcs_tuning_set": [_i32, _i32, _i32],
     "rcs_profile_read": [_i32, _P(_i64), _P(_i64), _P(_d), _P(_d), _P(_d)],
     "rcs_mlp_adam": [_vp, _vp, _vp, _vp, _i32, _i32, C.c_float, C.c_float, C.c_float,
@@ -384,6 +385,13 @@ def mlp_adam(w, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, str
 # ------------------------------------------------------------- measurement
 def profile_enable(every):
     _check(_lib.rcs_profile_enable(int(every)))
+
+
+def profile_event_floor():
+    """Seconds of an empty kernel timed like a probed launch."""
+    v = _d()
+    _check(_lib.rcs_profile_event_floor(C.byref(v)))
+    return v.value
 
 
 def profile_read(kclass):

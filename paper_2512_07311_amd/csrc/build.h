@@ -38,6 +38,6 @@ void mlp_forward(const float* w, const float* x, int batch, float* out, float* a
 
 // Reduced-precision two-site products (complex64 or split-bf16 on MFMA).
 void contract_two_site_lowp(const double2* A, const double2* B, double2* T, int dl, int dm, int dr,
-                            int precision, hipStream_t s);
+                            int precision, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 }  // namespace rcs

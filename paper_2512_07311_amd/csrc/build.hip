@@ -122,11 +122,11 @@ void contract_two_site(const double2* A, const double2* B, double2* T, int dl, i
                        hipStream_t s) {
   Probe pr(kKcTwoSite, s, 32.0 * dl * (double)dm * dr, 16.0 * (2.0 * dl * dm + 2.0 * dm * dr + 4.0 * dl * dr));
   if (precision != RCS_PREC_C128) {
-    contract_two_site_lowp(A, B, T, dl, dm, dr, precision, s);
+    contract_two_site_lowp(A, B, T, dl, dm, dr, precision, s, pr.start(), pr.stop());
     return;
   }
-  hipLaunchKernelGGL(k_two_site_f64, dim3(ceil_div(dr, GT_N), ceil_div(dl, GT_M), 4), dim3(GT_THREADS), 0, s, A, B,
-                     T, dl, dm, dr);
+  hipExtLaunchKernelGGL(k_two_site_f64, dim3(ceil_div(dr, GT_N), ceil_div(dl, GT_M), 4), dim3(GT_THREADS), 0, s,
+                        pr.start(), pr.stop(), 0, A, B, T, dl, dm, dr);
   HIP_LAUNCH_OK();
 }
 

@@ -13,6 +13,8 @@
 // MFMA layouts (lane l): f32 16x16x4: A[l%16][l/16], B[l/16][l%16];
 // bf16 16x16x32: A[l%16][8(l/16)+j], B[8(l/16)+j][l%16], j = 0..7;
 // both: D[4(l/16)+r][l%16].
+#include <hip/hip_ext.h>
+
 #include "build.h"
 #include "gemm_f64.h"
 
@@ -157,12 +159,13 @@ __global__ __launch_bounds__(256) void k_two_site_lowp(const double2* A, const d
 }
 
 void contract_two_site_lowp(const double2* A, const double2* B, double2* T, int dl, int dm, int dr,
-                            int precision, hipStream_t s) {
+                            int precision, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   dim3 grid(ceil_div(dr, CT_N), ceil_div(dl, CT_M), 4);
   if (precision == RCS_PREC_C64)
-    hipLaunchKernelGGL(k_two_site_lowp<RCS_PREC_C64>, grid, dim3(256), 0, s, A, B, T, dl, dm, dr);
+    hipExtLaunchKernelGGL(k_two_site_lowp<RCS_PREC_C64>, grid, dim3(256), 0, s, start, stop, 0, A, B, T, dl, dm, dr);
   else
-    hipLaunchKernelGGL(k_two_site_lowp<RCS_PREC_SPLIT_BF16>, grid, dim3(256), 0, s, A, B, T, dl, dm, dr);
+    hipExtLaunchKernelGGL(k_two_site_lowp<RCS_PREC_SPLIT_BF16>, grid, dim3(256), 0, s, start, stop, 0, A, B, T, dl,
+                          dm, dr);
   HIP_LAUNCH_OK();
 }
 

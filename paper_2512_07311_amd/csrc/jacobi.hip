@@ -568,17 +568,19 @@ static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bo
     {
       Probe pr(kKcJacGram, stream, fl, by);
       if (pl.jb == 16)
-        hipLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, a);
+        hipExtLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(), pr.stop(), 0, a);
       else
-        hipLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, a);
+        hipExtLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(), pr.stop(), 0, a);
     }
     HIP_LAUNCH_OK();
     {
       Probe pr(kKcJacRotate, stream, fl, 2.0 * by);
       if (pl.jb == 16)
-        hipLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, a);
+        hipExtLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, pr.start(),
+                              pr.stop(), 0, a);
       else
-        hipLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, a);
+        hipExtLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, pr.start(),
+                              pr.stop(), 0, a);
     }
     HIP_LAUNCH_OK();
   }

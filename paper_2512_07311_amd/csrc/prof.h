@@ -1,6 +1,10 @@
 // Sampled kernel timing: every `every`-th launch of a timed kernel class is
-// bracketed by HIP events on the stream it is launched on.
+// timed by start/stop events attached to the launch itself
+// (hipExtLaunchKernelGGL), on the stream it is launched on, so the interval
+// is the kernel's execution and not the gaps around it.
 #pragma once
+
+#include <hip/hip_ext.h>
 
 #include "common.h"
 
@@ -15,17 +19,21 @@ enum KernelClass : int {
   kKcCount = 5
 };
 
-// RAII probe: construct before the launch, destroy after it.
+// RAII probe: construct before the launch, pass start()/stop() to
+// hipExtLaunchKernelGGL (null when this launch is not sampled), destroy
+// after it.
 class Probe {
  public:
   Probe(int kclass, hipStream_t s, double flops, double bytes);
   ~Probe();
   Probe(const Probe&) = delete;
   Probe& operator=(const Probe&) = delete;
+  hipEvent_t start() const { return e0_; }
+  hipEvent_t stop() const { return e1_; }
 
  private:
   int slot_ = -1;
-  hipStream_t s_ = nullptr;
+  hipEvent_t e0_ = nullptr, e1_ = nullptr;
 };
 
 }  // namespace rcs

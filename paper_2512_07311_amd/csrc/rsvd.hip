@@ -358,7 +358,8 @@ void range_finder(const double2* M, int ldx, int len, int cnt, int l, int q, uin
   {
     // nominal work of the first sketch product M Z (complex fp32 GEMM)
     Probe pr(kKcRange, s, 8.0 * len * (double)cnt * l, 16.0 * len * (double)cnt + 8.0 * (double)(len + cnt) * l);
-    hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
+    hipExtLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, pr.start(), pr.stop(), 0, M, ldx, len, cnt, w.Z, w.ldz, l,
+                          w.Q, w.ldq);
   }
   HIP_LAUNCH_OK();
   orth(w.Q, w.ldq, len, l, w, s);

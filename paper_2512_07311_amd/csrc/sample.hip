@@ -184,7 +184,7 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
         const double fl = 16.0 * S * (double)ca.dl * ca.dr;
         const double by = 16.0 * (2.0 * ca.dl * ca.dr + (double)S * ca.dl + 2.0 * S * ca.dr);
         Probe pr(kKcChainGemm, st.stream, fl, by);
-        hipLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, ca);
+        hipExtLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, pr.start(), pr.stop(), 0, ca);
       }
       HIP_LAUNCH_OK();
       DecideArgs da;
