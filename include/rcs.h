@@ -284,7 +284,7 @@ rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float
  * 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram, 2 Jacobi rotation,
  * 3 two-site contraction, 4 randomized range finder. */
 rcs_status rcs_profile_enable(int32_t every);
-/* Mean event interval (seconds, host output) of 32 back-to-back launches of
+/* Median event interval (seconds, host output) of back-to-back launches of
  * an empty one-workgroup kernel on the null stream, timed the same way: the
  * floor of any probed launch time (dispatch and event overhead). */
 rcs_status rcs_profile_event_floor(double* seconds);

@@ -1,7 +1,9 @@
 // Sampled kernel timing probes (see prof.h).
 #include "prof.h"
 
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 namespace rcs {
 
@@ -130,23 +132,25 @@ rcs_status rcs_profile_event_floor(double* seconds) {
   try {
     RCS_REQUIRE(seconds, "null output");
     // back-to-back launches (as probed kernels run in a busy queue), each
-    // with its own event pair; the first loads the code object
-    constexpr int N = 33;
-    hipEvent_t e[2 * N];
-    for (int i = 0; i < 2 * N; ++i) HIP_OK(hipEventCreate(&e[i]));
+    // with its own event pair; the median interval of the last 128 (the
+    // first launches load the code object and start an idle queue)
+    constexpr int N = 160, M = 128;
+    std::vector<hipEvent_t> e(2 * N);
+    for (auto& x : e) HIP_OK(hipEventCreate(&x));
     for (int i = 0; i < N; ++i) {
       hipExtLaunchKernelGGL(rcs::k_prof_null, dim3(1), dim3(64), 0, nullptr, e[2 * i], e[2 * i + 1], 0, 0);
       HIP_OK(hipGetLastError());
     }
     HIP_OK(hipEventSynchronize(e[2 * N - 1]));
-    double tot = 0.0;
-    for (int i = 1; i < N; ++i) {
+    std::vector<double> iv;
+    for (int i = N - M; i < N; ++i) {
       float ms = 0.f;
       HIP_OK(hipEventElapsedTime(&ms, e[2 * i], e[2 * i + 1]));
-      tot += ms * 1e-3;
+      iv.push_back(ms * 1e-3);
     }
-    for (int i = 0; i < 2 * N; ++i) (void)hipEventDestroy(e[i]);
-    *seconds = tot / (N - 1);
+    for (auto& x : e) (void)hipEventDestroy(x);
+    std::sort(iv.begin(), iv.end());
+    *seconds = 0.5 * (iv[M / 2 - 1] + iv[M / 2]);
   } catch (const rcs::Error& e) {
     rcs::set_last_error(e.what());
     return e.status;
