@@ -1298,9 +1298,15 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
         auto st = std::make_unique<rcs_state_s>();
         st->stream = s;
         st->device = dev;
-        rcs::state_alloc(*st, circuits[i]->n, chi[i]);
-        rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], bo, *ws);
-        HIP_OK(hipStreamSynchronize(s));
+        try {
+          rcs::state_alloc(*st, circuits[i]->n, chi[i]);
+          rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], bo, *ws);
+          HIP_OK(hipStreamSynchronize(s));
+        } catch (...) {
+          // let queued work finish before the state and workspaces are freed
+          (void)hipStreamSynchronize(s);
+          throw;
+        }
         st->stream = caller;
         states[i] = std::move(st);
       }
@@ -1309,6 +1315,13 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
       std::lock_guard<std::mutex> lk(err_mu);
       if (err_status == RCS_OK) {
         err_status = e.status;
+        err_msg = e.what();
+      }
+      stop = true;
+    } catch (const std::exception& e) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (err_status == RCS_OK) {
+        err_status = RCS_ERR_DEVICE;
         err_msg = e.what();
       }
       stop = true;

@@ -2,6 +2,7 @@
 #include "prof.h"
 
 #include <algorithm>
+#include <list>
 #include <mutex>
 #include <vector>
 
@@ -24,7 +25,7 @@ std::mutex g_mu;
 int g_every = 0;
 int64_t g_counter[kKcCount] = {0};
 Totals g_tot[kKcCount];
-std::vector<Pending> g_pending;
+std::list<Pending> g_pending;   // list: a probe's entry stays valid while others drain
 std::vector<hipEvent_t> g_pool;
 
 hipEvent_t get_event() {
@@ -40,32 +41,30 @@ hipEvent_t get_event() {
 
 // Resolve finished probes (caller holds the lock; syncs when `wait`).
 void drain(bool wait) {
-  std::vector<Pending> keep;
-  for (auto& p : g_pending) {
+  for (auto it = g_pending.begin(); it != g_pending.end();) {
+    Pending& p = *it;
     if (!p.closed) {
-      keep.push_back(p);
+      ++it;
       continue;
     }
-    if (wait) HIP_OK(hipEventSynchronize(p.e1));
-    else if (hipEventQuery(p.e1) != hipSuccess) {
-      keep.push_back(p);
+    if (wait) {
+      HIP_OK(hipEventSynchronize(p.e1));
+    } else if (hipEventQuery(p.e1) != hipSuccess) {
+      ++it;
       continue;
     }
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.e0, p.e1) != hipSuccess) {   // launch failed: events never recorded
-      g_pool.push_back(p.e0);
-      g_pool.push_back(p.e1);
-      continue;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {   // else the launch failed: never recorded
+      Totals& t = g_tot[p.kclass];
+      t.timed += 1;
+      t.seconds += ms * 1e-3;
+      t.flops += p.flops;
+      t.bytes += p.bytes;
     }
-    Totals& t = g_tot[p.kclass];
-    t.timed += 1;
-    t.seconds += ms * 1e-3;
-    t.flops += p.flops;
-    t.bytes += p.bytes;
     g_pool.push_back(p.e0);
     g_pool.push_back(p.e1);
+    it = g_pending.erase(it);
   }
-  g_pending.swap(keep);
 }
 }  // namespace
 
@@ -75,18 +74,18 @@ Probe::Probe(int kclass, hipStream_t s, double flops, double bytes) {
   g_tot[kclass].launches += 1;
   if ((g_counter[kclass]++ % g_every) != 0) return;
   if (g_pending.size() > 4096) drain(false);
-  Pending p{get_event(), get_event(), kclass, flops, bytes, false};
-  g_pending.push_back(p);
-  slot_ = (int)g_pending.size() - 1;
-  e0_ = p.e0;
-  e1_ = p.e1;
+  g_pending.push_back(Pending{get_event(), get_event(), kclass, flops, bytes, false});
+  Pending* p = &g_pending.back();
+  entry_ = p;
+  e0_ = p->e0;
+  e1_ = p->e1;
   (void)s;
 }
 
 Probe::~Probe() {
-  if (slot_ < 0) return;
+  if (!entry_) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_pending[slot_].closed = true;
+  static_cast<Pending*>(entry_)->closed = true;
 }
 
 }  // namespace rcs

@@ -32,7 +32,7 @@ class Probe {
   hipEvent_t stop() const { return e1_; }
 
  private:
-  int slot_ = -1;
+  void* entry_ = nullptr;   // its pending record (stable until this probe closes it)
   hipEvent_t e0_ = nullptr, e1_ = nullptr;
 };
 
