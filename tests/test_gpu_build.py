@@ -112,3 +112,28 @@ def test_reduced_precision_build_error_budget(env, precision, rows, cols, cyc, s
     bar = 2e-4 if eps == 0.0 else max(2e-4, u * truncated_tolerance(om) / 1e-13)
     assert err < bar, (err, bar)
     assert g.info().canonical == 1
+
+
+@pytest.mark.parametrize("rows,cols,cyc,chi,eps", [
+    (8, 8, 2, 2, 0.0),      # 64 qubits: every bit of the uint64 bitstring is used
+    (3, 3, 6, 1, 0.0),      # bond cap 1: every cut truncated to a product state
+    (2, 3, 0, 8, 0.0),      # no cycles: the final single-qubit layer only
+])
+def test_build_edge_cases(env, rows, cols, cyc, chi, eps):
+    """Degenerate and maximal builds against the oracle MPS: amplitudes on
+    random bitstrings, estimated fidelity, and bit-exact shots from the
+    built state (high bit included at 64 qubits)."""
+    rcs, torch = env
+    c = rcs.Circuit(rows, cols, cyc, 5)
+    g = rcs.State.build(c, chi, eps)
+    om = mps.build(oc.Circuit(rows, cols, cyc, 5), chi, eps)
+    b = inputs.random_bitstrings(c.n, 500, seed=31)
+    err = normwise_rel(_amps(torch, g, b), om.amplitudes(b))
+    assert err < truncated_tolerance(om), err
+    assert abs(g.info().log_fidelity_est - om.log_fest) < 1e-10
+    o = oracle_state_from(g.to_host())
+    bits = torch.zeros(2000, dtype=torch.int64, device="cuda")
+    g.sample(bits, seed=17)
+    ob, _, tight = sample.sample(o, 2000, 17)
+    ok, n_exempt, _ = compare_shots(bits.cpu().numpy().view(np.uint64), ob, tight)
+    assert ok and n_exempt == 0
