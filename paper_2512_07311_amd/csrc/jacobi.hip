@@ -282,11 +282,18 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double2* part = a.part + (int64_t)p * a.n_gchunks * JP * JP;
   for (int e = tid; e < JP * JP; e += ROT_THREADS) {
+    // partials summed in chunk order; loads issued eight at a time
     double2 s = make_double2(0.0, 0.0);
-    for (int c = 0; c < a.n_gchunks; ++c) {
-      const double2 t = part[(int64_t)c * JP * JP + e];
-      s.x += t.x;
-      s.y += t.y;
+    for (int c0 = 0; c0 < a.n_gchunks; c0 += 8) {
+      double2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        t[u] = c0 + u < a.n_gchunks ? part[(int64_t)(c0 + u) * JP * JP + e] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s.x += t[u].x;
+        s.y += t[u].y;
+      }
     }
     const int i = e / JP, j = e % JP;
     G[i][j] = s;

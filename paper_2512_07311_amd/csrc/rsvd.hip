@@ -11,7 +11,8 @@
 // cores (v_mfma_f32_16x16x4f32); orth() keeps the basis in fp64: block
 // classical Gram-Schmidt with two passes (BCGS2) over 64-column panels and
 // two Cholesky-QR passes inside each panel (fp64 Gram, 64x64 Cholesky in LDS
-// with a pivot guard that zeroes numerically dependent columns).  The caller
+// with a pivot guard that zeroes numerically dependent columns); the power
+// iteration's intermediate bases take one pass of each.  The caller
 // then takes the exact fp64 SVD of the projected matrix B = Q^H M (their
 // Algorithm 5.1).
 #include "build.h"
@@ -189,11 +190,17 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
   __shared__ double dmax;
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += 256) {
+    // partials summed in chunk order; loads issued eight at a time
     double2 s = make_double2(0.0, 0.0);
-    for (int c = 0; c < n_chunks; ++c) {
-      const double2 t = part[(int64_t)c * 4096 + e];
-      s.x += t.x;
-      s.y += t.y;
+    for (int c0 = 0; c0 < n_chunks; c0 += 8) {
+      double2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = c0 + u < n_chunks ? part[(int64_t)(c0 + u) * 4096 + e] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s.x += t[u].x;
+        s.y += t[u].y;
+      }
     }
     const int i = e / 64, j = e % 64;
     R[i][j] = (i < pw && j < pw) ? s : make_double2(i == j ? 1.0 : 0.0, 0.0);
@@ -201,10 +208,10 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
   }
   if (tid < 64) dead[tid] = tid >= pw;
   __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < pw; ++i) m = fmax(m, R[i][i].x);
-    dmax = m;
+  if (tid < 64) {   // max of the diagonal over wave 0
+    double m = tid < pw ? R[tid][tid].x : 0.0;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (tid == 0) dmax = m;
   }
   __syncthreads();
   const int ty = tid >> 4, tx = tid & 15;
@@ -212,24 +219,29 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
     const double d = R[k][k].x;
     const bool dk = !(d > guard * dmax) || dead[k];
     if (!dk) {
-      const double rd = 1.0 / d;
-      for (int i = k + 1 + ty; i < pw; i += 16) {
-        const double2 a = R[k][i];
-        for (int j = k + 1 + tx; j < pw; j += 16) {
-          if (j >= i) {
-            const double2 b = R[k][j];
-            const double re = (a.x * b.x + a.y * b.y) * rd, im = (a.x * b.y - a.y * b.x) * rd;
-            R[i][j] = make_double2(R[i][j].x - re, R[i][j].y - im);
+      const double rd = rcp_fast(d);
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int i = k + 1 + ty + 16 * ii;
+        if (i < pw) {
+          const double2 a = R[k][i];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const int j = k + 1 + tx + 16 * jj;
+            if (j < pw && j >= i) {
+              const double2 b = R[k][j];
+              const double re = (a.x * b.x + a.y * b.y) * rd, im = (a.x * b.y - a.y * b.x) * rd;
+              R[i][j] = make_double2(R[i][j].x - re, R[i][j].y - im);
+            }
           }
         }
       }
     }
     __syncthreads();
-    const double p = dk ? 0.0 : sqrt(d);
-    const double rp = dk ? 0.0 : 1.0 / p;
+    const double rp = dk ? 0.0 : rsqrt_fast(d);
     if (tid > k && tid < pw) R[k][tid] = make_double2(R[k][tid].x * rp, R[k][tid].y * rp);
     if (tid == k) {
-      R[k][k] = make_double2(p, 0.0);
+      R[k][k] = make_double2(dk ? 0.0 : d * rp, 0.0);
       dead[k] = dk ? 1 : 0;
     }
   }
@@ -239,10 +251,14 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
   for (int i = pw - 1; i >= 0; --i) {
     double2 acc = make_double2(0.0, 0.0);
     if (c < pw && c >= i) {
-      for (int j = i + 1 + part4; j <= c; j += 4) {
-        const double2 a = R[i][j], b = Ri[j][c];
-        acc.x += a.x * b.x - a.y * b.y;
-        acc.y += a.x * b.y + a.y * b.x;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = i + 1 + part4 + 4 * q;
+        if (j <= c) {
+          const double2 a = R[i][j], b = Ri[j][c];
+          acc.x += a.x * b.x - a.y * b.y;
+          acc.y += a.x * b.y + a.y * b.x;
+        }
       }
     }
     acc.x += __shfl_xor(acc.x, 1);
@@ -253,7 +269,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chu
       if (dead[i] || dead[c]) {
         Ri[i][c] = make_double2(0.0, 0.0);
       } else {
-        const double rd = 1.0 / R[i][i].x;
+        const double rd = rcp_fast(R[i][i].x);
         Ri[i][c] = make_double2(((i == c ? 1.0 : 0.0) - acc.x) * rd, -acc.y * rd);
       }
     }
@@ -281,14 +297,18 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_apply(double2* Q, int ldq,
 }
 
 // Orthonormalise the l columns of Y (len x l, col-major, ld ldq) in place.
-static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s) {
-  // at most 8 row chunks: the single-workgroup Cholesky sums the partials
-  const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 8)), 64);
+// passes = 2: BCGS2 with CholQR2 panels (orthonormal to fp64 rounding, for
+// the final basis); passes = 1: one projection and one CholQR pass (a
+// well-conditioned basis of the same span, enough for the power
+// iteration's intermediate bases, which only carry the subspace).
+static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s, int passes) {
+  // at most 16 row chunks: the single-workgroup Cholesky sums the partials
+  const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 16)), 64);
   const int n_chunks = ceil_div(len, rows_per_chunk);
   for (int j0 = 0; j0 < l; j0 += 64) {
     const int pw = std::min(64, l - j0);
     if (j0 > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < passes; ++pass) {
         // split the length-len reduction over row chunks so ~256 workgroups run
         const int ny = ceil_div(j0, GT_M);
         const int n_kc = std::max(1, std::min({kMaxKChunks, 256 / ny, ceil_div(len, 128)}));
@@ -311,7 +331,7 @@ static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s
         HIP_LAUNCH_OK();
       }
     }
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
       hipLaunchKernelGGL(k_panel_gram, dim3(n_chunks), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, rows_per_chunk,
                          w.gpart);
       HIP_LAUNCH_OK();
@@ -362,14 +382,14 @@ void range_finder(const double2* M, int ldx, int len, int cnt, int l, int q, uin
                           w.Q, w.ldq);
   }
   HIP_LAUNCH_OK();
-  orth(w.Q, w.ldq, len, l, w, s);
+  orth(w.Q, w.ldq, len, l, w, s, q > 0 ? 1 : 2);
   for (int it = 0; it < q; ++it) {
     hipLaunchKernelGGL(k_mhq32, gz, dim3(256), 0, s, M, ldx, len, cnt, w.Q, w.ldq, l, w.Z, w.ldz);
     HIP_LAUNCH_OK();
-    orth(w.Z, w.ldz, cnt, l, w, s);
+    orth(w.Z, w.ldz, cnt, l, w, s, 1);
     hipLaunchKernelGGL(k_mz32, gy, dim3(256), 0, s, M, ldx, len, cnt, w.Z, w.ldz, l, w.Q, w.ldq);
     HIP_LAUNCH_OK();
-    orth(w.Q, w.ldq, len, l, w, s);
+    orth(w.Q, w.ldq, len, l, w, s, it + 1 == q ? 2 : 1);
   }
 }
 
