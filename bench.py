@@ -253,7 +253,6 @@ def main():
     t1 = time.time()
     prof = [rcs.profile_read(k) for k in range(len(rcs.KERNEL_CLASSES))]
     rcs.profile_enable(0)
-    floor = rcs.profile_event_floor()
     st, t_sample, xeb, se = res[-1]
     inf = st.info()
     sec = (t1 - t0) / args.steps
@@ -278,7 +277,6 @@ def main():
             "intensity_flop_per_byte": intensity, "dtype": dt,
             "kernel": p["name"], "kernel_source_sha": source_hash(p["name"]),
             "avg_launch_us": 1e6 * p["seconds"] / max(p["timed"], 1),
-            "event_floor_us": 1e6 * floor,
             "launches_per_step": p["launches"] // max(args.steps, 1),
             "kernel_share_of_step": est[dom] / max(t1 - t0, 1e-9)})
     out = {
