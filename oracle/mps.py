@@ -132,9 +132,14 @@ class MPS:
         cl, cr = a.shape[0], b.shape[2]
         return thetap.transpose(1, 0, 2, 3).reshape(2 * cl, 2 * cr), cl, cr
 
-    def update(self, i, G, chi, eps, tag=None):
+    def update(self, i, G, chi, eps, tag=None, perturb=None):
+        """perturb: None for every reference value; otherwise a function
+        applied to the two-site matrix before its SVD, used only to measure
+        how strongly a schedule amplifies a small per-step error."""
         self.move_center(i, i + 1)
         M, cl, cr = self.two_site_matrix(i, G)
+        if perturb is not None:
+            M = perturb(M)
         U, s, Vh = np.linalg.svd(M, full_matrices=False)
         k, eps_step, w, _ = rank_rule(s, chi, eps)
         nk = np.sqrt(np.sum(s[:k] ** 2))
@@ -192,8 +197,9 @@ class MPS:
         return worst
 
 
-def build(circ, chi, eps, max_ops=None):
-    """Run the whole schedule; returns the right-canonical MPS."""
+def build(circ, chi, eps, max_ops=None, perturb=None):
+    """Run the whole schedule; returns the right-canonical MPS.  `perturb`
+    is passed to every truncating update (None: the plain method)."""
     pi, ops = schedule(circ)
     st = MPS(circ.n, pi)
     for oi, op in enumerate(ops):
@@ -206,7 +212,7 @@ def build(circ, chi, eps, max_ops=None):
         else:
             _, i, kind, t = op
             G = circ.gate2 if kind == "fsim" else SWAP
-            st.update(i, G, chi, eps, tag=(oi, t))
+            st.update(i, G, chi, eps, tag=(oi, t), perturb=perturb)
             if kind == "swap":
                 st.swap_positions(i)
     st.right_canonicalize()

@@ -47,9 +47,30 @@ def truncated_tolerance(om):
     (sqrt(m) u times the sweep count of a Jacobi or bidiagonal method), so the
     bar is 1e-13 times the summed conditioning of the cuts, never below 1e-10.
     """
+    return max(1e-10, 1e-13 * cut_conditioning(om.records))
+
+
+def cut_conditioning(records):
+    """Sum over the truncated cuts of s_k / (s_k - s_{k+1}) (1-based k kept):
+    the first-order amplification of a backward error into the kept
+    subspace, summed along the schedule."""
     kappa = 0.0
-    for rec in om.records:
+    for rec in records:
         s, k = rec["spectrum"], rec["k"]
         if k < len(s) and s[k] > 1e-12 * s[0] and s[k - 1] > s[k]:
             kappa += s[k - 1] / (s[k - 1] - s[k])
-    return max(1e-10, 1e-13 * kappa)
+    return kappa
+
+
+def relative_noise(delta, seed):
+    """A perturbation for the oracle's truncating updates: adds seeded
+    Gaussian noise of relative Frobenius size delta to each two-site matrix
+    before its SVD.  Rebuilding with it measures how strongly a schedule
+    amplifies a per-step error of that size (the scale of another correct
+    implementation's rounding)."""
+    g = np.random.default_rng(seed)
+
+    def perturb(m):
+        e = g.standard_normal(m.shape) + 1j * g.standard_normal(m.shape)
+        return m + (delta * np.linalg.norm(m) / np.linalg.norm(e)) * e
+    return perturb

@@ -25,11 +25,12 @@ def _svd_gpu(rcs, torch, M):
     return s.cpu().numpy(), u.cpu().numpy().T
 
 
-# up to the shapes of saturated cuts: 2 chi x 2 chi at chi = 1024, and the
-# widest matrix the rank kernel takes (4096 columns, chi = 2048)
+# up to the shapes of saturated cuts: 2 chi x 2 chi at chi = 1024 and at the
+# largest cap, chi = 2048 (4096 columns, the widest the rank kernel takes)
 SHAPES = [(37, 23, "gauss"), (100, 100, "gauss"), (300, 64, "gauss"), (64, 300, "gauss"),
           (513, 257, "gauss"), (256, 256, "decay"), (200, 120, "rank40"), (1, 5, "gauss"),
-          (7, 1, "gauss"), (2048, 2048, "decay"), (4096, 700, "gauss"), (700, 4096, "gauss")]
+          (7, 1, "gauss"), (2048, 2048, "decay"), (4096, 700, "gauss"), (700, 4096, "gauss"),
+          (4096, 4096, "decay")]
 
 
 @pytest.mark.parametrize("ln,cnt,kind", SHAPES)
