@@ -8,9 +8,9 @@ namespace rcs {
 constexpr int kMaxKChunks = 16;   // row chunks of the Gram-Schmidt projections
 
 struct RsvdWork {
-  DevBuf bufQ, bufZ, bufC, bufCp, bufPp, bufG, bufR;
+  DevBuf bufQ, bufZ, bufC, bufCp, bufPp, bufG, bufR, bufGs;
   double2 *Q = nullptr, *Z = nullptr, *C = nullptr, *Cpart = nullptr, *Ppart = nullptr, *gpart = nullptr,
-          *Rinv = nullptr;
+          *Rinv = nullptr, *gsum = nullptr;
   int ldq = 0, ldz = 0, ldc = 0;
 };
 

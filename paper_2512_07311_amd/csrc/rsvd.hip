@@ -154,7 +154,7 @@ __global__ void k_ysub_apply(double2* Y, int ldq, int len, int j0, int pw, const
 }
 
 // G (64 x 64) = Yp^H Yp for the panel (partial over row chunks, summed in
-// fixed order by the Cholesky kernel).
+// fixed chunk order by k_gsum).
 __global__ __launch_bounds__(GT_THREADS) void k_panel_gram(const double2* Q, int ldq, int len, int j0, int pw,
                                                           int rows_per_chunk, double2* part) {
   __shared__ SmemC64 sm;
@@ -175,6 +175,22 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_gram(const double2* Q, int
   acc_foreach(acc, [&](int r, int c, double re, double im) { g[r * 64 + c] = make_double2(re, im); });
 }
 
+// G = sum of the panel Gram's row-chunk partials (at most 16), one element
+// per thread, added in chunk order; all loads of a thread issue together.
+__global__ __launch_bounds__(256) void k_gsum(const double2* part, int n_chunks, double2* G) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  double2 t[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) t[u] = u < n_chunks ? part[(int64_t)u * 4096 + e] : make_double2(0.0, 0.0);
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    acc.x += t[u].x;
+    acc.y += t[u].y;
+  }
+  G[e] = acc;
+}
+
 // Cholesky G = R^H R (R upper triangular) with pivot guard, then Rinv = R^-1.
 // A pivot below guard * max(diag) marks the column dependent: its row of R
 // is set to zero and its column of Rinv to zero, so the panel column becomes 0.
@@ -182,29 +198,22 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_gram(const double2* Q, int
 // the unscaled row k and its pivot d (R_ij -= conj(R_ki) R_kj / d), and row k
 // is scaled afterwards, while step k+1 touches only rows > k.  The inverse
 // solves R Rinv = I bottom-up, one row per step, four lanes per column.
-__global__ __launch_bounds__(256) void k_chol_inv(const double2* part, int n_chunks, int pw, double guard,
-                                                 double2* Rinv) {
+__global__ __launch_bounds__(256) void k_chol_inv(const double2* G, int pw, double guard, double2* Rinv) {
   __shared__ double2 R[64][65];
   __shared__ double2 Ri[64][65];
   __shared__ int dead[64];
   __shared__ double dmax;
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    // partials summed in chunk order; loads issued eight at a time
-    double2 s = make_double2(0.0, 0.0);
-    for (int c0 = 0; c0 < n_chunks; c0 += 8) {
-      double2 t[8];
+  {
+    double2 g[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = c0 + u < n_chunks ? part[(int64_t)(c0 + u) * 4096 + e] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 16; ++u) g[u] = G[tid + 256 * u];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        s.x += t[u].x;
-        s.y += t[u].y;
-      }
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e / 64, j = e % 64;
+      R[i][j] = (i < pw && j < pw) ? g[u] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+      Ri[i][j] = make_double2(0.0, 0.0);
     }
-    const int i = e / 64, j = e % 64;
-    R[i][j] = (i < pw && j < pw) ? s : make_double2(i == j ? 1.0 : 0.0, 0.0);
-    Ri[i][j] = make_double2(0.0, 0.0);
   }
   if (tid < 64) dead[tid] = tid >= pw;
   __syncthreads();
@@ -302,9 +311,10 @@ __global__ __launch_bounds__(GT_THREADS) void k_panel_apply(double2* Q, int ldq,
 // well-conditioned basis of the same span, enough for the power
 // iteration's intermediate bases, which only carry the subspace).
 static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s, int passes) {
-  // at most 16 row chunks: the single-workgroup Cholesky sums the partials
+  // at most 16 row chunks (k_gsum sums them)
   const int rows_per_chunk = (int)round_up(std::max(64, ceil_div(len, 16)), 64);
   const int n_chunks = ceil_div(len, rows_per_chunk);
+  RCS_REQUIRE(n_chunks >= 1 && n_chunks <= 16, "panel Gram split into more than 16 row chunks");
   for (int j0 = 0; j0 < l; j0 += 64) {
     const int pw = std::min(64, l - j0);
     if (j0 > 0) {
@@ -335,7 +345,9 @@ static void orth(double2* Y, int ldq, int len, int l, RsvdWork& w, hipStream_t s
       hipLaunchKernelGGL(k_panel_gram, dim3(n_chunks), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw, rows_per_chunk,
                          w.gpart);
       HIP_LAUNCH_OK();
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, w.gpart, n_chunks, pw, 1e-26, w.Rinv);
+      hipLaunchKernelGGL(k_gsum, dim3(16), dim3(256), 0, s, w.gpart, n_chunks, w.gsum);
+      HIP_LAUNCH_OK();
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, w.gsum, pw, 1e-26, w.Rinv);
       HIP_LAUNCH_OK();
       hipLaunchKernelGGL(k_panel_apply, dim3(1, ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, Y, ldq, len, j0, pw,
                          w.Rinv);
@@ -358,11 +370,13 @@ void rsvd_work_ensure(RsvdWork& w, int len, int cnt, int l) {
   const int n_chunks = ceil_div(mx, (int)round_up(std::max(64, ceil_div(mx, 64)), 64)) + 1;
   w.bufG.ensure((size_t)n_chunks * 4096 * sizeof(double2));
   w.bufR.ensure((size_t)4096 * sizeof(double2));
+  w.bufGs.ensure((size_t)4096 * sizeof(double2));
   w.Q = w.bufQ.as<double2>();
   w.Z = w.bufZ.as<double2>();
   w.C = w.bufC.as<double2>();
   w.gpart = w.bufG.as<double2>();
   w.Rinv = w.bufR.as<double2>();
+  w.gsum = w.bufGs.as<double2>();
   w.ldq = ldq;
   w.ldz = ldz;
 }
