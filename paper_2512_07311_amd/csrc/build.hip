@@ -310,8 +310,9 @@ __global__ __launch_bounds__(1024) void k_sort_rank(const double* sigma, int cnt
     int k_eps = cnt;
     double tail_at[1];
     (void)tail_at;
-    // tail(cnt) = 0 always qualifies; walk down accumulating.
-    double tail_k = 0.0;
+    // walk down accumulating; tail(cnt) is the outside weight, so when even
+    // that exceeds eps w the scan stops at once and k_eps = cnt discards it
+    double tail_k = extra;
     for (int k = cnt; k >= 1; --k) {
       // tail currently = tail(k)
       if (tail <= eps * w) {
@@ -843,6 +844,28 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   HIP_LAUNCH_OK();
   hipLaunchKernelGGL(k_sub_scalar, dim3(1), dim3(1), 0, s, sc + 0, sc + 1, sc + 2);
   HIP_LAUNCH_OK();
+  // Early rejection, the same decision as the judge below.  When the weight
+  // outside span(Q) exceeds eps times the total, no rank meets eps, so the
+  // rank rule keeps k = min(l, cap).  The discarded fraction is then at
+  // least (outside weight) / (total), and if that alone exceeds the judge's
+  // threshold the split would be rejected after its projected SVD anyway.
+  // The 1e-9 relative margins cover the rounding between ||B||_F^2 and the
+  // sum of B's squared singular values.
+  if (o.fallback_tau >= 0.0) {
+    double h[3];
+    HIP_OK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double outside = std::max(h[2], 0.0), wb = outside + h[1];
+    if (wb > 0.0 && outside > eps * wb * (1.0 + 1e-9)) {
+      const int k_forced = std::min(l, cap);
+      const double ep = (o.rank_mode == RCS_RANK_LEARNED) ? predicted_eps(y, k_forced, m) : ctx.prev_eps[i];
+      if (outside / wb > (std::max(eps, ep) + o.fallback_tau) * (1.0 + 1e-9)) {
+        st.n_fallback += 1;
+        st.n_rsvd_early += 1;
+        return false;
+      }
+    }
+  }
   std::vector<double> spec;
   SplitResult r = svd_split(st, ws, pl, cap, eps, true, log_spectra ? &spec : nullptr, sc + 2);
   const double eps_pred = (o.rank_mode == RCS_RANK_LEARNED) ? predicted_eps(y, r.k, m) : ctx.prev_eps[i];
@@ -1017,7 +1040,8 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
     if (every > 0.0) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
       if (el >= next_report) {
-        std::fprintf(stderr, "rcs build: op %d/%d, %.1f s\n", oi, stop, el);
+        std::fprintf(stderr, "rcs build: op %d/%d, %.1f s (randomized: %d accepted, %d rejected, %d of them early)\n",
+                     oi, stop, el, st.n_rsvd_ok, st.n_fallback, st.n_rsvd_early);
         std::fflush(stderr);
         next_report = el + every;
       }

@@ -61,6 +61,7 @@ struct rcs_state_s {
   int device = 0;
   // bookkeeping
   int n_trunc = 0, n_fallback = 0, n_rsvd_ok = 0, jacobi_sweeps_max = 0;
+  int n_rsvd_early = 0;   // fall-backs decided before the projected SVD
   double log_fest = 0.0, sum_eps = 0.0;
   double build_seconds = 0.0, svd_seconds = 0.0;
   std::vector<rcs::SpectrumRecord> spectra;

@@ -158,6 +158,43 @@ def test_randomized_build_fidelity(env, mode):
     assert f_true >= 0.5 * f_true_plain, msg
 
 
+def test_overconfident_network_is_caught_by_the_judge(env):
+    """A network that predicts a discarded fraction of 1e-12 at every rank
+    sizes the sketch far too small, so the weight outside its subspace is
+    large.  That weight is discarded even when no rank meets eps, and it must
+    be counted: the judge then rejects those splits, and the estimated
+    fidelity of what it accepts stays faithful to the true one (same band as
+    the plain build's).  Counting no discarded weight when no rank meets eps
+    would accept them and leave F_est near 1 while the true fidelity
+    collapses."""
+    from oracle import circuit as oc, dense
+    from paper_2512_07311_amd import learn
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 10, 41)
+    plain = rcs.State.build(c, 32, 1e-9)
+    w = np.zeros(len(learn.he_init(0)), dtype=np.float32)
+    w[-32:] = -12.0                      # output biases: log10 fraction -12
+    g = rcs.State.build(c, 32, 1e-9, rank_mode=1, mlp_weights=w, fallback_tau=1e-6, rsvd_oversample=4)
+    inf, pinf = g.info(), plain.info()
+    assert inf.n_fallbacks > 0
+    psi = dense.simulate(oc.Circuit(4, 5, 10, 41))
+    bits = torch.arange(1 << c.n, dtype=torch.int64, device="cuda")
+
+    def fid(st):
+        amps = torch.zeros(1 << c.n, 2, dtype=torch.float64, device="cuda")
+        st.amplitudes(bits, amps)
+        a = amps.cpu().numpy()
+        return abs(np.vdot(psi, a[:, 0] + 1j * a[:, 1])) ** 2
+
+    f_true, f_true_plain = fid(g), fid(plain)
+    f_est, f_est_plain = np.exp(inf.log_fidelity_est), np.exp(pinf.log_fidelity_est)
+    msg = "true %.4g est %.4g | plain true %.4g est %.4g | accepted %d fallbacks %d" % (
+        f_true, f_est, f_true_plain, f_est_plain, inf.n_rsvd_accepted, inf.n_fallbacks)
+    r_plain = f_true_plain / f_est_plain
+    assert 0.5 * r_plain <= f_true / f_est <= 2.0 * r_plain, msg
+    assert f_true >= 0.5 * f_true_plain, msg
+
+
 def test_training_reduces_loss(env):
     from paper_2512_07311_amd import learn
     rcs, torch = env
