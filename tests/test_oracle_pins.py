@@ -444,6 +444,25 @@ def test_rsvd_interlacing_and_hmt_bound():
     assert err <= bound
 
 
+def test_rsvd_rank_counts_weight_outside_the_sketch():
+    """A sketch narrower than the rank leaves weight outside span(Q).  When
+    even keeping every sketched direction leaves more than eps of the total,
+    no rank meets eps: the rule keeps all l directions (or the cap), and
+    the discarded fraction is exactly the weight outside the sketch, never
+    zero."""
+    s_full = 0.8 ** np.arange(40)
+    fro2 = float(np.sum(s_full ** 2))
+    s = s_full[:6]                               # an exact 6-column sketch
+    outside = float(np.sum(s_full[6:] ** 2)) / fro2
+    k, e = rsvd.rsvd_rank(s, fro2, 32, 1e-9)     # cap above the sketch width
+    assert k == 6 and abs(e - outside) < 1e-15 and e > 1e-9
+    k, e = rsvd.rsvd_rank(s, fro2, 4, 1e-9)      # cap below it
+    assert k == 4 and abs(e - float(np.sum(s_full[4:] ** 2)) / fro2) < 1e-15
+    # when the sketch holds nearly all the weight, the usual eps rank applies
+    k, e = rsvd.rsvd_rank(s_full[:30], fro2, 32, 1e-4)
+    assert e <= 1e-4 and k == int(np.argmax(1.0 - np.cumsum(s_full ** 2) / fro2 <= 1e-4)) + 1
+
+
 def test_sketch_entries_are_unit_phases():
     om = rsvd.sketch(50, 20, seed=9, step=3)
     assert np.all(np.isin(np.round(om, 12), [1, 1j, -1, -1j]))
