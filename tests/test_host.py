@@ -86,3 +86,42 @@ def test_invalid_arguments(rcs, kw, msg):
     with pytest.raises(rcs.RcsError) as ei:
         rcs.Circuit(**kw)
     assert ei.value.status == 1 and msg in str(ei.value)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark covers one GPU: asking for more exits with status 2 and
+    says so, before any GPU work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_without_a_gpu_fails_loudly():
+    """No silent CPU path: without a GPU the benchmark exits non-zero and
+    prints no result line."""
+    import subprocess
+    import sys
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu-baseline"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode != 0
+    assert "needs a GPU" in r.stderr and '"metric"' not in r.stdout
+
+
+def test_binding_without_the_library_raises(tmp_path):
+    """The Python binding has no fallback: loaded from a folder without
+    librcs.so it raises ImportError instead of importing."""
+    import importlib.util
+    import shutil
+    pkg = tmp_path / "pkg_without_lib"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2512_07311_amd", "__init__.py"), pkg / "__init__.py")
+    spec = importlib.util.spec_from_file_location("pkg_without_lib", str(pkg / "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="librcs.so is not built"):
+        spec.loader.exec_module(mod)
