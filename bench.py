@@ -5,37 +5,48 @@ One step = build the MPS output state of the 53-qubit (6x9 grid minus one
 seed-chosen site), 14-cycle ABCDCDAB circuit at bond cap chi = 1024, draw
 1,000,000 shots from it, and score them by linear XEB (self-XEB from the
 shots' own log2 probabilities).  `value` is the whole step's throughput in
-shots per second; the state-build seconds and the sampling rate are reported
-beside it.  Inputs (the circuit description, the shot buffers) are resident
-before the timed region starts.
+shots per second of the plain form (complex128 contractions, fp64 full SVD);
+the state-build seconds and the sampling rate are reported beside it, and
+so is one step of the learned form (split-bf16 contractions,
+network-predicted ranks, fp32 randomized range finder with the fp64 judge),
+timed the same way.  Inputs (the circuit description, the shot buffers) are
+resident before the timed region starts.
 
-Forms: "plain" = complex128 contractions and the fp64 full SVD; "learned" =
-split-bf16 contractions, network-predicted ranks, fp32 randomized range
-finder with fp64 fall-back (weights from --mlp, or trained before the timed
-region on spectra of a differently seeded circuit).
+Wall-clock budget: one full step takes minutes, so --steps and --warmup are
+upper limits.  The warm-up runs on the 30-qubit chi-256 circuit (it loads
+every kernel class, and its logged spectra train the rank network); timed
+steps continue only while the next one, the learned step and the CPU
+baseline still fit in --budget-s seconds from process start.  The line
+reports the steps and warm-ups actually run.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form plain|learned]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
 """
-import argparse
-import json
-import os
-import sys
 import time
+
+T_PROC0 = time.time()
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+CPU_BASELINE_S = 25.0     # wall-clock of the oracle sample
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget from process start; steps stop when the next would overrun")
     ap.add_argument("--workload", default="rcs53_6x9_c14_chi1024")
     ap.add_argument("--shots", type=int, default=None)
-    ap.add_argument("--form", default="plain", choices=["plain", "learned"])
+    ap.add_argument("--form", default="both", choices=["plain", "learned", "both"])
     ap.add_argument("--mlp", default=None, help=".npy packed network weights (learned form)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--profile-every", type=int, default=16)
@@ -44,6 +55,14 @@ def parse():
     ap.add_argument("--hbm-copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 8 device-to-device copies of MIB MiB (scales rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
+
+
+def elapsed():
+    return time.time() - T_PROC0
+
+
+def log(msg):
+    print("bench [%6.1f s]: %s" % (elapsed(), msg), file=sys.stderr, flush=True)
 
 
 # the source file of each probed kernel class (its hash ties counter data to
@@ -75,46 +94,67 @@ def measured_traffic(kernel, workload, form):
     return None
 
 
-def cpu_baseline(wl, seed, budget_s=20.0):
+def cpu_baseline(wl, seed, update_shapes, budget_s=CPU_BASELINE_S):
     """The oracle (numpy fp64) timed on a bounded sample of the same workload
-    and scaled to end-to-end shots/s for the full schedule and shot count:
-    one saturated two-site update at half the bond cap (cost scales as
-    chi^3: x8), and chain-rule shots on an MPS with the workload's bond
-    profile."""
+    and scaled to end-to-end shots/s: two-site updates timed at three bond
+    sizes give a power law in the SVD's m n min(m, n), which is summed over
+    the real shapes of every update of the GPU build; chain-rule shots on an
+    MPS with the workload's bond profile give the per-shot time."""
     import numpy as np
     from oracle import circuit as oc, mps, sample
     from tests import inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     c = oc.Circuit(wl["rows"], wl["cols"], wl["cycles"], seed, n_removed_random=wl["removed_random"])
-    _, ops = mps.schedule(c)
-    n_upd = sum(1 for o in ops if o[0] == "u")
-    chi = wl["chi"]
-    half = max(1, chi // 2)
-    g = inputs.rng(11)
-    st = mps.MPS(3, [0, 1, 2])
-    shp = [(half, 2, half), (half, 2, half), (half, 2, half)]
-    st.A = [(g.standard_normal(s_) + 1j * g.standard_normal(s_)) / np.sqrt(2 * half) for s_ in shp]
-    st.center = 1
-    t0 = time.time()
-    st.update(0, c.gate2, half, wl["eps"])
-    t_upd = (time.time() - t0) * 8.0
-    dims = [1] + [min(2 ** min(k, c.n - k), chi) for k in range(1, c.n)] + [1]
+    t_begin = time.time()
+
+    def cost(dl, dr):
+        m, n = 2 * dl, 2 * dr
+        return float(m) * n * min(m, n)
+
+    def time_update(d):
+        g = inputs.rng(11 + d)
+        st = mps.MPS(3, [0, 1, 2])
+        shp = (d, 2, d)
+        st.A = [(g.standard_normal(shp) + 1j * g.standard_normal(shp)) / np.sqrt(2 * d) for _ in range(3)]
+        st.center = 1
+        t0 = time.time()
+        st.update(0, c.gate2, d, wl["eps"])
+        return time.time() - t0
+
+    time_update(32)                    # first-call overheads out of the fit
+    sizes, times = [], []
+    for d in (128, 256, 512):
+        t = time_update(d)
+        sizes.append(cost(d, d))
+        times.append(t)
+        if time.time() - t_begin > 0.6 * budget_s:
+            break
+    if len(sizes) >= 2:
+        p, logc = np.polyfit(np.log(sizes), np.log(times), 1)
+    else:
+        p, logc = 1.0, np.log(times[0] / sizes[0])
+    t_updates = float(sum(np.exp(logc) * cost(int(u[2]), int(u[4])) ** p for u in update_shapes))
+    dims = [1] + [min(2 ** min(k, c.n - k), wl["chi"]) for k in range(1, c.n)] + [1]
     A = inputs.random_site_tensors(dims, seed=12)
     st2 = mps.MPS(c.n, list(range(c.n)))
     st2.A = [a / np.sqrt(2 * a.shape[2]) for a in A]
     t1 = time.time()
     n_sh = 0
-    while time.time() - t1 < budget_s * 0.4 or n_sh == 0:
+    while time.time() - t1 < max(0.3 * budget_s, 1.0) or n_sh == 0:
         sample.sample(st2, 8, seed=1003, first_shot=n_sh)
         n_sh += 8
     t_shot = (time.time() - t1) / n_sh
     shots = wl["shots"]
-    total = n_upd * t_upd + shots * t_shot
+    total = t_updates + shots * t_shot
     return {"value": shots / total, "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": ("numpy fp64 oracle on %d host threads: one two-site update at chi=%d "
-                       "(%.2f s, x8 for chi=%d, x%d updates) + %d chain-rule shots on a chi=%d "
-                       "bond profile (%.4f s each, x%d shots); extrapolated end-to-end"
-                       % (threads, half, t_upd / 8, chi, n_upd, n_sh, chi, t_shot, shots))}
+            "sample": ("numpy fp64 oracle on %d host threads: two-site updates timed at chi %s "
+                       "(%s s), fitted t = c (m n min(m,n))^%.2f and summed over the %d real update "
+                       "shapes of the GPU build (%.0f s); %d chain-rule shots on a chi=%d bond profile "
+                       "(%.4f s each, x%d shots); %.0f s of CPU time measured"
+                       % (threads, [int(round((s / 8) ** (1 / 3))) for s in sizes],
+                          ", ".join("%.2f" % t for t in times), p, len(update_shapes), t_updates, n_sh,
+                          wl["chi"], t_shot, shots, time.time() - t_begin)),
+            "projected_build_s": t_updates, "per_shot_s": t_shot}
 
 
 def batch_step_fn(rcs, torch, wl, args):
@@ -135,12 +175,11 @@ def batch_step_fn(rcs, torch, wl, args):
         states = rcs.State.build_batch(circs, chis, [wl["eps"]] * len(circs), **kw)
         torch.cuda.synchronize()
         t_b = time.time()
-        print("bench: %d states built in %.1f s" % (len(states), t_b - t0), file=sys.stderr, flush=True)
+        log("%d states built in %.1f s" % (len(states), t_b - t0))
         rcs.sample_batch(states, shots, 1004, bits, l2)
         xs = [rcs.xeb_log2(c.n, l2[i])[0] for i, c in enumerate(circs)]
         torch.cuda.synchronize()
-        print("bench: %d x %d shots sampled and scored in %.2f s" % (len(states), shots, time.time() - t_b),
-              file=sys.stderr, flush=True)
+        log("%d x %d shots sampled and scored in %.2f s" % (len(states), shots, time.time() - t_b))
         return states, t_b - t0, time.time() - t_b, xs
     return specs, step
 
@@ -178,14 +217,45 @@ def main_batch(args, wl):
     print(json.dumps(out), flush=True)
 
 
+def svd_roofline(prof, inf, floor_s, steps):
+    """Roofline of the fp64 factorisation kernels (the Jacobi Gram and
+    rotation passes, which together do every SVD and centre move of the
+    build): algorithmic work = the nominal flops of those factorisations
+    (thin SVD 4 (14 m n^2 + 8 n^3) per update, Householder QR
+    4 (2 m n^2 - 2 n^3 / 3) per centre move); time = each class's probed
+    average launch time, less the event floor, times its launches."""
+    by = {p["name"]: p for p in prof}
+    t_total, launches, detail = 0.0, 0, {}
+    for name in ("k_jac_gram", "k_jac_rotate"):
+        p = by[name]
+        if not p["timed"]:
+            continue
+        avg = p["seconds"] / p["timed"]
+        avg_c = max(avg - floor_s, 0.0)
+        t_total += avg_c * p["launches"]
+        launches += p["launches"]
+        detail[name] = {"avg_launch_us": 1e6 * avg_c, "avg_launch_us_event": 1e6 * avg,
+                        "launches_per_step": p["launches"] // max(steps, 1)}
+    work = steps * (inf.nominal_svd_flops + inf.nominal_qr_flops)
+    achieved = work / t_total if t_total > 0 else 0.0
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAKS["fp64"], "traffic": None,
+            "kernel": "k_jac_gram + k_jac_rotate (fp64 SVDs and centre moves)",
+            "kernel_source_sha": source_hash("k_jac_rotate"), "dtype": "fp64",
+            "work_per_step_flop": inf.nominal_svd_flops + inf.nominal_qr_flops,
+            "nominal_svd_flop": inf.nominal_svd_flops, "nominal_qr_flop": inf.nominal_qr_flops,
+            "kernel_seconds_per_step": t_total / max(steps, 1), "event_floor_us": 1e6 * floor_s,
+            "per_kernel": detail}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    # the state build reports its progress on stderr every 20 s
-    os.environ.setdefault("RCS_PROGRESS", "20")
+    # the state build reports its progress on stderr every 30 s
+    os.environ.setdefault("RCS_PROGRESS", "30")
     import numpy as np
     import torch
     if not torch.cuda.is_available():
@@ -211,95 +281,129 @@ def main():
     shots = args.shots or wl["shots"]
     circ = rcs.Circuit(wl["rows"], wl["cols"], wl["cycles"], args.seed,
                        n_removed_random=wl["removed_random"])
-    kw = dict(contraction="c128", rank_mode=0)
-    mlp_w = None
-    if args.form == "learned":
-        kw = dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6)
-        if args.mlp:
-            mlp_w = np.load(args.mlp).astype(np.float32)
-        else:
-            from paper_2512_07311_amd import learn
-            tr = inputs.WORKLOADS["rcs30_5x6_c14_chi256"]
-            tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1)
-            st = rcs.State.build(tc, tr["chi"], tr["eps"], log_spectra=True)
-            X, Y = learn.dataset(st.spectra(), tc.n, tr["cycles"], torch)
-            print("bench: %d training spectra logged" % X.shape[0], file=sys.stderr, flush=True)
-            mlp_w, _ = learn.train(X, Y, torch, steps=1500, batch=256, seed=args.seed)
-            print("bench: rank network trained", file=sys.stderr, flush=True)
-            del st
-        kw["mlp_weights"] = mlp_w
+    stream = torch.cuda.current_stream()
     bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
     log2p = torch.zeros(shots, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
+    run_plain = args.form in ("plain", "both")
+    run_learned = args.form in ("learned", "both")
+    log("library loaded; workload %s, %d qubits, %d updates" % (args.workload, circ.n, circ.n_updates))
 
-    def step():
+    # ---- warm-up on the 30-qubit chi-256 circuit (every kernel class); its
+    # logged spectra are the rank network's training data
+    tr = inputs.WORKLOADS["rcs30_5x6_c14_chi256"]
+    tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1)
+    n_warm = 0
+    mlp_w = None
+    if args.warmup > 0 or (run_learned and not args.mlp):
+        wst = rcs.State.build(tc, tr["chi"], tr["eps"], log_spectra=run_learned and not args.mlp,
+                              stream=stream)
+        wbits = torch.zeros(tr["shots"], dtype=torch.int64, device="cuda")
+        wl2 = torch.zeros(tr["shots"], dtype=torch.float64, device="cuda")
+        wst.sample(wbits, wl2, seed=1003)
+        rcs.xeb_log2(tc.n, wl2)
+        torch.cuda.synchronize()
+        n_warm = 1 if args.warmup > 0 else 0
+        log("warm-up: 30-qubit chi-256 build + %d shots done" % tr["shots"])
+        if run_learned and not args.mlp:
+            from paper_2512_07311_amd import learn
+            X, Y = learn.dataset(wst.spectra(), tc.n, tr["cycles"], torch)
+            mlp_w, _ = learn.train(X, Y, torch, steps=1500, batch=256, seed=args.seed)
+            log("rank network trained on %d spectra" % X.shape[0])
+        del wst
+    if run_learned and args.mlp:
+        mlp_w = np.load(args.mlp).astype(np.float32)
+    floor_s = rcs.profile_event_floor()
+
+    def step(kw):
         st = rcs.State.build(circ, wl["chi"], wl["eps"], stream=stream, max_ops=args.max_ops, **kw)
-        print("bench: state built in %.1f s" % st.info().build_seconds, file=sys.stderr, flush=True)
+        t_build = st.info().build_seconds
+        log("state built in %.1f s" % t_build)
         t_b = time.time()
         st.sample(bits, log2p, seed=1003)
         x, se = rcs.xeb_log2(circ.n, log2p)
         torch.cuda.synchronize()
-        print("bench: %d shots sampled and scored in %.2f s" % (shots, time.time() - t_b), file=sys.stderr,
-              flush=True)
-        return st, time.time() - t_b, x, se
+        t_s = time.time() - t_b
+        log("%d shots sampled and scored in %.2f s" % (shots, t_s))
+        return st, t_s, x, se
 
-    for _ in range(args.warmup):
-        step()
+    plain_kw = dict(contraction="c128", rank_mode=0)
+    learned_kw = dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w)
+    main_kw = plain_kw if run_plain else learned_kw
+    reserve_cpu = 0.0 if args.no_cpu_baseline else CPU_BASELINE_S + 10.0
+
+    # ---- timed region: whole steps of the main form
     rcs.profile_enable(args.profile_every)
     torch.cuda.synchronize()
     t0 = time.time()
-    res = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
+    res = []
+    t_step = None
+    while len(res) < max(1, args.steps):
+        if res:
+            reserve = reserve_cpu + ((1.2 * t_step + 30.0) if (run_plain and run_learned) else 0.0)
+            if elapsed() + 1.15 * t_step + reserve > args.budget_s:
+                log("budget: stopping after %d timed steps" % len(res))
+                break
+        ts = time.time()
+        res.append(step(main_kw))
+        torch.cuda.synchronize()
+        t_step = time.time() - ts
     t1 = time.time()
     prof = [rcs.profile_read(k) for k in range(len(rcs.KERNEL_CLASSES))]
     rcs.profile_enable(0)
+    n_steps = len(res)
     st, t_sample, xeb, se = res[-1]
     inf = st.info()
-    sec = (t1 - t0) / args.steps
-    # dominant kernel: largest estimated total time (timed share scaled up)
-    est = [p["seconds"] * (p["launches"] / p["timed"]) if p["timed"] else 0.0 for p in prof]
-    dom = int(np.argmax(est))
-    p = prof[dom]
-    dt = {0: "fp64", 1: "fp64", 2: "fp64", 3: {"c128": "fp64", "c64": "fp32", "split_bf16": "bf16"}.get(
-        kw["contraction"], "fp64"), 4: "fp32"}[dom]
-    # the roof is set by the kernel's algorithmic intensity against the ridge
-    # point of its datatype: below it the kernel is bound by HBM bandwidth
-    intensity = p["flops"] / max(p["bytes"], 1.0)
-    if intensity < PEAKS[dt] / PEAKS["hbm"]:
-        achieved = p["bytes"] / p["seconds"] if p["seconds"] > 0 else 0.0
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAKS["hbm"]}
-    else:
-        achieved = p["flops"] / p["seconds"] if p["seconds"] > 0 else 0.0
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[dt] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAKS[dt]}
-    roof.update({"traffic": measured_traffic(p["name"], args.workload, args.form),
-            "intensity_flop_per_byte": intensity, "dtype": dt,
-            "kernel": p["name"], "kernel_source_sha": source_hash(p["name"]),
-            "avg_launch_us": 1e6 * p["seconds"] / max(p["timed"], 1),
-            "launches_per_step": p["launches"] // max(args.steps, 1),
-            "kernel_share_of_step": est[dom] / max(t1 - t0, 1e-9)})
+    upd = st.updates()
+    sec = (t1 - t0) / n_steps
+    roof = svd_roofline(prof, inf, floor_s, n_steps)
+    est = {p["name"]: p["seconds"] * (p["launches"] / p["timed"]) if p["timed"] else 0.0 for p in prof}
+    roof["factorisation_share_of_step"] = roof["kernel_seconds_per_step"] / sec
     out = {
         "metric": "state-build s + shots/s per MI355X at chi=1024, learned/FP32 vs plain FP64, XEB",
-        "value": shots / sec, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": shots / sec, "unit": "shots/s", "n_gpus": 1, "steps": n_steps, "warmup": n_warm,
         "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.form == "plain" else "bf16x3/f32/f64",
+        "dtype": "f64" if run_plain else "bf16x3/f32/f64",
         "data": "synthetic (seeded random circuit)",
         "config": {"workload": args.workload, "qubits": circ.n, "cycles": wl["cycles"], "chi": wl["chi"],
-                   "eps": wl["eps"], "shots": shots, "form": args.form, "contraction": kw["contraction"],
-                   "circuit_seed": args.seed, "max_ops": args.max_ops},
+                   "eps": wl["eps"], "shots": shots, "form": "plain" if run_plain else "learned",
+                   "contraction": main_kw["contraction"], "circuit_seed": args.seed, "max_ops": args.max_ops,
+                   "warmup_workload": "rcs30_5x6_c14_chi256" if n_warm else None},
+        "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
         "state_build_s": inf.build_seconds, "sample_shots_per_s": shots / t_sample,
         "self_xeb": xeb, "self_xeb_stderr": se, "log_fidelity_est": inf.log_fidelity_est,
-        "max_bond": inf.max_bond, "n_fallbacks": inf.n_fallbacks, "n_rsvd_accepted": inf.n_rsvd_accepted,
+        "fidelity_est": float(np.exp(inf.log_fidelity_est)),
+        "max_bond": inf.max_bond, "n_updates": int(len(upd)), "n_center_moves": inf.n_center_moves,
         "roofline": roof,
         "kernels": {q["name"]: {"launches": q["launches"], "timed": q["timed"],
-                                "avg_us": 1e6 * q["seconds"] / max(q["timed"], 1),
-                                "flop_per_launch": q["flops"] / max(q["timed"], 1),
-                                "bytes_per_launch": q["bytes"] / max(q["timed"], 1),
-                                "est_total_s": e} for q, e in zip(prof, est)},
+                                "avg_us_event": 1e6 * q["seconds"] / max(q["timed"], 1),
+                                "est_total_s": est[q["name"]]} for q in prof},
     }
+    del res, st
+
+    # ---- the learned form, one step, timed the same way (outside the timed region)
+    if run_plain and run_learned:
+        if elapsed() + 1.2 * sec + reserve_cpu <= args.budget_s:
+            ts = time.time()
+            lst, lt_sample, lxeb, lse = step(learned_kw)
+            torch.cuda.synchronize()
+            lsec = time.time() - ts
+            li = lst.info()
+            out["learned"] = {
+                "step_s": lsec, "shots_per_s": shots / lsec, "state_build_s": li.build_seconds,
+                "sample_shots_per_s": shots / lt_sample, "self_xeb": lxeb, "self_xeb_stderr": lse,
+                "log_fidelity_est": li.log_fidelity_est, "fidelity_est": float(np.exp(li.log_fidelity_est)),
+                "fest_rel_diff_vs_plain": float(np.exp(li.log_fidelity_est - inf.log_fidelity_est) - 1.0),
+                "build_speedup_vs_plain": inf.build_seconds / li.build_seconds,
+                "n_rsvd_accepted": li.n_rsvd_accepted, "n_fallbacks": li.n_fallbacks,
+                "contraction": wl["precision"]}
+            del lst
+        else:
+            out["learned"] = {"skipped": "wall-clock budget"}
+            log("budget: learned step skipped")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.seed)
+        out["cpu_baseline"] = cpu_baseline(wl, args.seed, upd)
+        log("cpu baseline done")
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

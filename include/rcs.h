@@ -192,6 +192,10 @@ typedef struct {
   double build_seconds;    /* device time from first kernel to last       */
   double svd_seconds;      /* part spent in SVD/RSVD kernels (if timed)   */
   int64_t device_bytes;    /* MPS + workspace bytes held                  */
+  int32_t n_center_moves;  /* single-site orthogonalisations (centre moves) */
+  double nominal_svd_flops;/* sum over full SVDs of 4 (14 m n^2 + 8 n^3),    */
+                           /* m >= n the two-site matrix shape              */
+  double nominal_qr_flops; /* sum over centre moves of 4 (2 m n^2 - 2n^3/3) */
 } rcs_state_info;
 
 rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out);
@@ -223,6 +227,32 @@ void rcs_state_destroy(rcs_state s);
 rcs_status rcs_state_spectra(rcs_state s, int32_t* n_records, int64_t* n_values,
                              int32_t* meta_host, double* values_host);
 
+/* One record per two-site update of the build, in schedule order (always
+ * kept): records_host[7u..7u+6] = {position, cycle, chi_l, chi_m (middle
+ * bond before the update), chi_r, kept rank, path}, path 0 = full fp64 SVD,
+ * 1 = randomized split accepted, 2 = randomized split rejected by the judge
+ * and redone with the full SVD.  Capacity 7 * n_updates (query with NULL). */
+rcs_status rcs_state_updates(rcs_state s, int32_t* n_updates, int32_t* records_host);
+
+/* Decisions of every randomized split of a learned or rsvd-at-cap build, in
+ * order (the task's learned part: predicted rank, randomized truncated SVD,
+ * full-SVD judge).  Per record r:
+ *   ints_host[10r..10r+9] = {update index, position, cycle, m = min(rows,
+ *     cols) of the two-site matrix, k_hat, sketch width l, kept rank k (the
+ *     forced rank min(l, cap) for an early rejection, -1 when l >= m and the
+ *     plain split ran), accepted, early (rejected before the projected SVD
+ *     because the weight outside the sketched subspace already fails the
+ *     judge), number of logged projected singular values};
+ *   doubles_host[4r..4r+3] = {eps_pred at k, eps_rand (discarded fraction
+ *     incurred), weight outside span(Q), total weight ||M||_F^2};
+ *   net_host[98r..98r+97] = the 66 network inputs then its 32 outputs
+ *     (learned mode; zeros otherwise);
+ *   values_host: the projected singular values (descending, logging builds
+ *     only), concatenated in record order.
+ * Any output may be NULL; counts come back through n_records / n_values. */
+rcs_status rcs_state_rsvd_log(rcs_state s, int32_t* n_records, int64_t* n_values, int32_t* ints_host,
+                              double* doubles_host, float* net_host, double* values_host);
+
 /* -------------------------------------------------------- kernel-level calls
  * Exposed for parity tests of individual stages and for the training driver.
  * All device pointers, all ordered on `stream`. */
@@ -249,6 +279,12 @@ rcs_status rcs_two_site(int32_t dl, int32_t dm, int32_t dr, const double* a_dev,
  * fro2_host receives ||M||_F^2 (fp64). */
 rcs_status rcs_rsvd(int32_t len, int32_t cnt, const double* x_dev, int32_t l, int32_t q,
                     uint64_t seed, uint64_t step, double* s_dev, double* fro2_host, void* stream);
+
+/* The orthonormal basis Q of the same range finder (len x l, column-major
+ * complex, column j at q_dev + 2*len*j): the span whose projection
+ * rcs_rsvd decomposes.  Same arguments and errors as rcs_rsvd. */
+rcs_status rcs_rsvd_basis(int32_t len, int32_t cnt, const double* x_dev, int32_t l, int32_t q,
+                          uint64_t seed, uint64_t step, double* q_dev, void* stream);
 
 /* Spectrum features: 64-bin histogram of log10(s^2/sum s^2) (0.25 decade
  * bins over [-16,0), clamped) of s_dev[0..k-1], normalised to sum 1, then
@@ -299,8 +335,7 @@ const char* rcs_profile_class_name(int32_t kclass);
  * first entry with cnt <= cnt_max applies (block = 16 or 32 columns per
  * block, inner_sweeps in [1, 8] two-sided sweeps per block-pair meeting).
  * Process-wide; written by the autotuner (paper_2512_07311_amd/autotune.py)
- * from device timings.  Without entries: block 32 for cnt >= 512, else 16;
- * one inner sweep. */
+ * from device timings.  Without entries: block 16, one inner sweep. */
 rcs_status rcs_tuning_set(int32_t cnt_max, int32_t block, int32_t inner_sweeps);
 void rcs_tuning_clear(void);
 

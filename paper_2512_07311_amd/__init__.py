@@ -61,7 +61,9 @@ class StateInfo(C.Structure):
                 ("n_fallbacks", C.c_int32), ("n_rsvd_accepted", C.c_int32),
                 ("jacobi_sweeps_max", C.c_int32), ("log_fidelity_est", C.c_double),
                 ("sum_eps", C.c_double), ("build_seconds", C.c_double),
-                ("svd_seconds", C.c_double), ("device_bytes", C.c_int64)]
+                ("svd_seconds", C.c_double), ("device_bytes", C.c_int64),
+                ("n_center_moves", C.c_int32), ("nominal_svd_flops", C.c_double),
+                ("nominal_qr_flops", C.c_double)]
 
 
 _vp, _i32, _i64, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -87,9 +89,12 @@ _SIGS = {
     "rcs_state_export": [_vp, _P(_d), _i64, _P(_i64)],
     "rcs_state_import": [_i32, _P(_i32), _P(_i32), _P(_d), _i32, _vp, _P(_vp)],
     "rcs_state_spectra": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d)],
+    "rcs_state_updates": [_vp, _P(_i32), _P(_i32)],
+    "rcs_state_rsvd_log": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d), _P(C.c_float), _P(_d)],
     "rcs_svd_jacobi": [_i32, _i32, _vp, _vp, _vp, _vp],
     "rcs_two_site": [_i32, _i32, _i32, _vp, _vp, _P(_d), _i32, _vp, _vp],
     "rcs_rsvd": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _P(_d), _vp],
+    "rcs_rsvd_basis": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _vp],
     "rcs_spectrum_features": [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp],
     "rcs_spectrum_targets": [_vp, _i32, _vp, _vp],
     "rcs_mlp_forward": [_vp, _vp, _i32, _vp, _vp],
@@ -293,6 +298,42 @@ class State:
             o += m
         return out
 
+    def updates(self):
+        """(n_updates, 7) int32: position, cycle, chi_l, chi_m, chi_r, kept,
+        path (0 full SVD, 1 randomized accepted, 2 randomized rejected)."""
+        n = _i32()
+        _check(_lib.rcs_state_updates(self.h, C.byref(n), None))
+        rec = np.zeros(7 * max(n.value, 1), dtype=np.int32)
+        _check(_lib.rcs_state_updates(self.h, C.byref(n), rec.ctypes.data_as(_P(_i32))))
+        return rec[:7 * n.value].reshape(n.value, 7)
+
+    def rsvd_log(self):
+        """One dict per randomized split: the decisions of the learned path."""
+        nr, nv = _i32(), _i64()
+        _check(_lib.rcs_state_rsvd_log(self.h, C.byref(nr), C.byref(nv), None, None, None, None))
+        n = nr.value
+        ints = np.zeros(10 * max(n, 1), dtype=np.int32)
+        dbl = np.zeros(4 * max(n, 1), dtype=np.float64)
+        net = np.zeros(98 * max(n, 1), dtype=np.float32)
+        vals = np.zeros(max(nv.value, 1), dtype=np.float64)
+        _check(_lib.rcs_state_rsvd_log(self.h, C.byref(nr), C.byref(nv),
+                                       ints.ctypes.data_as(_P(_i32)), dbl.ctypes.data_as(_P(_d)),
+                                       net.ctypes.data_as(_P(C.c_float)),
+                                       vals.ctypes.data_as(_P(_d))))
+        out, o = [], 0
+        for r in range(n):
+            q = ints[10 * r:10 * r + 10]
+            d = dbl[4 * r:4 * r + 4]
+            nvr = int(q[9])
+            out.append(dict(update=int(q[0]), pos=int(q[1]), cycle=int(q[2]), m=int(q[3]),
+                            k_hat=int(q[4]), l=int(q[5]), k=int(q[6]), accepted=bool(q[7]),
+                            early=bool(q[8]), eps_pred=float(d[0]), eps_rand=float(d[1]),
+                            outside=float(d[2]), total=float(d[3]),
+                            feat=net[98 * r:98 * r + 66].copy(), y=net[98 * r + 66:98 * r + 98].copy(),
+                            values=vals[o:o + nvr].copy()))
+            o += nvr
+        return out
+
     def sample(self, bits, log2p=None, n_shots=None, seed=0, first_shot=0):
         """bits: uint64/int64 device tensor (n_shots,); log2p: float64 or None."""
         n_shots = bits.numel() if n_shots is None else n_shots
@@ -357,6 +398,12 @@ def rsvd(x, l, q, seed, step, s, stream=None):
     _check(_lib.rcs_rsvd(ln, cnt, _ptr(x), l, q, seed, step, _ptr(s), C.byref(f),
                          _stream_ptr(stream)))
     return f.value
+
+
+def rsvd_basis(x, l, q, seed, step, qout, stream=None):
+    """qout: complex128 device tensor (l, len) receiving the basis columns."""
+    cnt, ln = x.shape
+    _check(_lib.rcs_rsvd_basis(ln, cnt, _ptr(x), l, q, seed, step, _ptr(qout), _stream_ptr(stream)))
 
 
 def spectrum_features(s, k, bond, n_sites, cycle, n_cycles, feat, stream=None):

@@ -98,6 +98,9 @@ rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out) {
   inf.build_seconds = s->build_seconds;
   inf.svd_seconds = s->svd_seconds;
   inf.device_bytes = (int64_t)(s->slab.bytes + s->spare.bytes);
+  inf.n_center_moves = s->n_moves;
+  inf.nominal_svd_flops = s->nominal_svd_flops;
+  inf.nominal_qr_flops = s->nominal_qr_flops;
   *out = inf;
   RCS_API_END
 }
@@ -223,6 +226,66 @@ rcs_status rcs_state_spectra(rcs_state s, int32_t* n_records, int64_t* n_values,
       m[3] = r.kept;
       m[4] = r.chi_l;
       m[5] = r.chi_r;
+    }
+    if (values_host) std::copy(r.values.begin(), r.values.end(), values_host + o);
+    o += (int64_t)r.values.size();
+  }
+  RCS_API_END
+}
+
+rcs_status rcs_state_updates(rcs_state s, int32_t* n_updates, int32_t* records_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  if (n_updates) *n_updates = (int32_t)s->updates.size();
+  if (records_host)
+    for (size_t i = 0; i < s->updates.size(); ++i) {
+      const auto& u = s->updates[i];
+      int32_t* r = records_host + 7 * i;
+      r[0] = u.pos;
+      r[1] = u.cycle;
+      r[2] = u.chi_l;
+      r[3] = u.chi_m;
+      r[4] = u.chi_r;
+      r[5] = u.kept;
+      r[6] = u.path;
+    }
+  RCS_API_END
+}
+
+rcs_status rcs_state_rsvd_log(rcs_state s, int32_t* n_records, int64_t* n_values, int32_t* ints_host,
+                              double* doubles_host, float* net_host, double* values_host) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  int64_t nv = 0;
+  for (const auto& r : s->rsvd_log) nv += (int64_t)r.values.size();
+  if (n_records) *n_records = (int32_t)s->rsvd_log.size();
+  if (n_values) *n_values = nv;
+  int64_t o = 0;
+  for (size_t i = 0; i < s->rsvd_log.size(); ++i) {
+    const auto& r = s->rsvd_log[i];
+    if (ints_host) {
+      int32_t* q = ints_host + 10 * i;
+      q[0] = r.update;
+      q[1] = r.pos;
+      q[2] = r.cycle;
+      q[3] = r.m;
+      q[4] = r.k_hat;
+      q[5] = r.l;
+      q[6] = r.k;
+      q[7] = r.accepted;
+      q[8] = r.early;
+      q[9] = (int32_t)r.values.size();
+    }
+    if (doubles_host) {
+      double* d = doubles_host + 4 * i;
+      d[0] = r.eps_pred;
+      d[1] = r.eps_rand;
+      d[2] = r.outside;
+      d[3] = r.total;
+    }
+    if (net_host) {
+      std::copy(r.feat, r.feat + 66, net_host + 98 * i);
+      std::copy(r.y, r.y + 32, net_host + 98 * i + 66);
     }
     if (values_host) std::copy(r.values.begin(), r.values.end(), values_host + o);
     o += (int64_t)r.values.size();

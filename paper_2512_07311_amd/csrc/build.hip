@@ -567,6 +567,16 @@ __global__ void k_copy_out(const double2* X, int ldx, int len, int cnt, const in
   }
 }
 
+// q_dev[j * len + r] = Q[r][j]: the fp64 basis the range finder leaves.
+__global__ void k_copy_basis(const double2* Q, int ldq, int len, int l, double2* out) {
+  const int64_t tot = (int64_t)len * l;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % len), j = (int)(e / len);
+    out[e] = Q[(int64_t)j * ldq + r];
+  }
+}
+
 // Export layout (a, s, b) -> device layout [s][a][b]
 __global__ void k_to_device_layout(const double2* in, int da, int db, double2* out) {
   const int64_t tot = (int64_t)2 * da * db;
@@ -626,6 +636,8 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
                              double eps, bool renorm, std::vector<double>* spectrum_out,
                              const double* extra_dev = nullptr, bool ortho_only = false) {
   hipStream_t s = st.stream;
+  // the rank kernel sorts at most SORT_MAX values in LDS
+  RCS_REQUIRE(pl.cnt <= SORT_MAX, "matrix too wide for the rank kernel");
   double2* X = ws.X.as<double2>();
   // ||X||_F^2 scales the Jacobi's numerically-zero column threshold
   hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
@@ -649,7 +661,6 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
   hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
-  RCS_REQUIRE(pl.cnt <= SORT_MAX, "matrix too wide for the rank kernel");
   hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, cap, eps,
                      ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), extra_dev);
   HIP_LAUNCH_OK();
@@ -705,6 +716,18 @@ void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
   if (t_elems > 0) ws.T.ensure((size_t)t_elems * sizeof(double2));
 }
 
+// Nominal work of the factorisations (real flops, complex counted as 4x
+// real): thin SVD with U, Golub & Van Loan's count 14 m n^2 + 8 n^3, and
+// Householder QR 2 m n^2 - 2 n^3 / 3, m >= n.
+static double nominal_svd_flops(int a, int b) {
+  const double m = std::max(a, b), n = std::min(a, b);
+  return 4.0 * (14.0 * m * n * n + 8.0 * n * n * n);
+}
+static double nominal_qr_flops(int a, int b) {
+  const double m = std::max(a, b), n = std::min(a, b);
+  return 4.0 * (2.0 * m * n * n - 2.0 * n * n * n / 3.0);
+}
+
 // Move the orthogonality centre one step (exact orthogonalisation by SVD,
 // dropping only exact zeros).
 static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
@@ -722,6 +745,8 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   HIP_LAUNCH_OK();
   SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr, nullptr, true);
   const int k = r.k;
+  st.n_moves += 1;
+  st.nominal_qr_flops += nominal_qr_flops(len, cnt);
   hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
                      ws.wn_final, pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
   HIP_LAUNCH_OK();
@@ -800,21 +825,30 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
                              int cap, double eps, int cycle, bool log_spectra) {
   hipStream_t s = st.stream;
   const BuildOptions& o = *ctx.o;
-  const int dl = st.dims[i], dr = st.dims[i + 2];
+  const int dl = st.dims[i], dm = st.dims[i + 1], dr = st.dims[i + 2];
   const int len = 2 * dl, cnt = 2 * dr, m = std::min(len, cnt);
-  float y[32];
+  RsvdRecord rec{};
+  rec.update = ctx.update_index - 1;
+  rec.pos = i;
+  rec.cycle = cycle;
+  rec.m = m;
+  rec.k = -1;
+  float* y = rec.y;
   int k_hat;
   if (o.rank_mode == RCS_RANK_LEARNED) {
     spectrum_features(ctx.bond_spec.as<double>() + (size_t)i * ctx.chi_cap, ctx.bond_k[i], i, st.n, cycle,
                       ctx.n_cycles, ctx.feat.as<float>(), s);
     mlp_forward(ctx.w_mlp.as<float>(), ctx.feat.as<float>(), 1, ctx.yhat.as<float>(), nullptr, s);
-    HIP_OK(hipMemcpyAsync(y, ctx.yhat.p, sizeof(y), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(rec.y, ctx.yhat.p, sizeof(rec.y), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(rec.feat, ctx.feat.p, sizeof(rec.feat), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     k_hat = predict_rank(y, m, cap, eps);
   } else {
     k_hat = std::min(cap, m);
   }
   const int l = std::min(k_hat + std::max(0, o.rsvd_p), m);
+  rec.k_hat = k_hat;
+  rec.l = l;
   if (l >= m) return false;   // the sketch would cover the whole space: plain split
   // M (len x cnt, column-major) from the products
   const int ldm = (int)round_up(len, 64);
@@ -851,17 +885,24 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   // threshold the split would be rejected after its projected SVD anyway.
   // The 1e-9 relative margins cover the rounding between ||B||_F^2 and the
   // sum of B's squared singular values.
-  if (o.fallback_tau >= 0.0) {
+  {
     double h[3];
     HIP_OK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     const double outside = std::max(h[2], 0.0), wb = outside + h[1];
-    if (wb > 0.0 && outside > eps * wb * (1.0 + 1e-9)) {
+    rec.outside = outside;
+    rec.total = wb;
+    if (o.fallback_tau >= 0.0 && wb > 0.0 && outside > eps * wb * (1.0 + 1e-9)) {
       const int k_forced = std::min(l, cap);
       const double ep = (o.rank_mode == RCS_RANK_LEARNED) ? predicted_eps(y, k_forced, m) : ctx.prev_eps[i];
       if (outside / wb > (std::max(eps, ep) + o.fallback_tau) * (1.0 + 1e-9)) {
         st.n_fallback += 1;
         st.n_rsvd_early += 1;
+        rec.early = 1;
+        rec.k = k_forced;
+        rec.eps_pred = ep;
+        rec.eps_rand = outside / wb;
+        st.rsvd_log.push_back(rec);
         return false;
       }
     }
@@ -870,8 +911,14 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   SplitResult r = svd_split(st, ws, pl, cap, eps, true, log_spectra ? &spec : nullptr, sc + 2);
   const double eps_pred = (o.rank_mode == RCS_RANK_LEARNED) ? predicted_eps(y, r.k, m) : ctx.prev_eps[i];
   const bool accept = o.fallback_tau >= 0.0 && r.eps_step <= std::max(eps, eps_pred) + o.fallback_tau;
+  rec.k = r.k;
+  rec.eps_pred = eps_pred;
+  rec.eps_rand = r.eps_step;
+  rec.accepted = accept ? 1 : 0;
+  st.rsvd_log.push_back(rec);
   if (!accept) {
     st.n_fallback += 1;
+    if (log_spectra) st.rsvd_log.back().values = std::move(spec);
     return false;
   }
   const int k = r.k;
@@ -888,9 +935,11 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   st.n_rsvd_ok += 1;
   ctx.prev_eps[i] = r.eps_step;
   record_bond_spectrum(st, ws, ctx, i, k);
+  st.updates.push_back(UpdateRecord{i, cycle, dl, dm, dr, k, 1});
   if (log_spectra) {
-    SpectrumRecord rec{i, cycle, l, k, dl, dr, std::move(spec)};
-    st.spectra.push_back(std::move(rec));
+    st.rsvd_log.back().values = spec;
+    SpectrumRecord srec{i, cycle, l, k, dl, dr, std::move(spec)};
+    st.spectra.push_back(std::move(srec));
   }
   return true;
 }
@@ -905,9 +954,11 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
   ctx.update_index += 1;
   ws.T.ensure((size_t)4 * dl * dr * sizeof(double2));
   contract_two_site(st.site[i], st.site[i + 1], ws.T.as<double2>(), dl, dm, dr, precision, s);
+  const size_t n_log = st.rsvd_log.size();
   if (ctx.o && ctx.o->rank_mode != RCS_RANK_FULL_SVD &&
       randomized_split(st, ws, ctx, i, gate16, cap_eff, eps, cycle, log_spectra))
     return;
+  const bool randomized_tried = st.rsvd_log.size() > n_log;
   int orient;
   if (dr < dl)
     orient = 1;
@@ -929,12 +980,14 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
   std::vector<double> spec;
   SplitResult r = svd_split(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr);
   const int k = r.k;
+  st.nominal_svd_flops += nominal_svd_flops(len, cnt);
   record_bond_spectrum(st, ws, ctx, i, k);
   if (ctx.o) ctx.prev_eps[i] = r.eps_step;
   hipLaunchKernelGGL(k_write_split, dim3(grid1d((int64_t)2 * k * (dl + dr))), dim3(256), 0, s,
                      ws.wn_final, pl.ldx, ws.P.as<double2>(), pl.cnt, k, dl, dr, orient,
                      st.site[i], st.site[i + 1]);
   HIP_LAUNCH_OK();
+  st.updates.push_back(UpdateRecord{i, cycle, dl, dm, dr, k, randomized_tried ? 2 : 0});
   st.dims[i + 1] = k;
   st.center = orient == 1 ? i + 1 : i;
   st.log_fest += std::log1p(-r.eps_step);
@@ -1236,6 +1289,28 @@ rcs_status rcs_rsvd(int32_t len, int32_t cnt, const double* x_dev, int32_t l, in
                      ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
   HIP_LAUNCH_OK();
   HIP_OK(hipMemcpyAsync(s_dev, ws->sorted.p, l * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  RCS_API_END
+}
+
+rcs_status rcs_rsvd_basis(int32_t len, int32_t cnt, const double* x_dev, int32_t l, int32_t q, uint64_t seed,
+                          uint64_t step, double* q_dev, void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(x_dev && q_dev, "null pointer");
+  RCS_REQUIRE(len >= 1 && cnt >= 1 && l >= 1 && l <= cnt && l <= len && q >= 0 && cnt <= rcs::SORT_MAX,
+              "bad sizes");
+  hipStream_t s = rcs::as_stream(stream);
+  rcs::RsvdWork rw;
+  const int ldm = (int)rcs::round_up(len, 64);
+  rcs::DevBuf M;
+  M.ensure((size_t)ldm * cnt * sizeof(double2));
+  hipLaunchKernelGGL(rcs::k_copy_in, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x_dev), len, cnt, M.as<double2>(), ldm);
+  HIP_LAUNCH_OK();
+  rcs::range_finder(M.as<double2>(), ldm, len, cnt, l, q, seed, step, rw, s);
+  hipLaunchKernelGGL(rcs::k_copy_basis, dim3(rcs::grid1d((int64_t)len * l)), dim3(256), 0, s, rw.Q, rw.ldq, len, l,
+                     reinterpret_cast<double2*>(q_dev));
+  HIP_LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
   RCS_API_END
 }

@@ -69,6 +69,7 @@ void drain(bool wait) {
 }  // namespace
 
 Probe::Probe(int kclass, hipStream_t s, double flops, double bytes) {
+  if (kclass < 0 || kclass >= kKcCount) return;   // a launch that is never probed
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_every <= 0) return;
   g_tot[kclass].launches += 1;

@@ -150,12 +150,38 @@ __global__ void k_decide_grouped(const DecideArgs* groups) {
   if (m < a.S) decide_one(a, m);
 }
 
+int state_max_bond(const rcs_state_s& st) {
+  int maxd = 1;
+  for (int d : st.dims) maxd = std::max(maxd, d);
+  return maxd;
+}
+
+// Bytes of sampler workspace for S shots per pass at maximum bond maxd:
+// two ping-pong W buffers (S x 2 maxd complex), the per-shot partial norms
+// of every column tile of both branches, and the chosen branch per shot.
+size_t chain_work_bytes(int64_t S, int maxd) {
+  const int ntiles = ceil_div(maxd, GT_N);
+  return 2 * round_up((size_t)S * 2 * maxd * sizeof(double2), 256) +
+         round_up((size_t)2 * S * ntiles * sizeof(double), 256) + round_up((size_t)S, 256);
+}
+
+ChainBuffers chain_buffers_in(char* base, int64_t S, int maxd) {
+  const int ntiles = ceil_div(maxd, GT_N);
+  ChainBuffers b;
+  b.S0 = S;
+  const size_t wb = round_up((size_t)S * 2 * maxd * sizeof(double2), 256);
+  b.w[0] = reinterpret_cast<double2*>(base);
+  b.w[1] = reinterpret_cast<double2*>(base + wb);
+  b.part = reinterpret_cast<double*>(base + 2 * wb);
+  b.sel = reinterpret_cast<int8_t*>(base + 2 * wb + round_up((size_t)2 * S * ntiles * sizeof(double), 256));
+  return b;
+}
+
 void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed, int mode,
                uint64_t* bits_dev, double* log2p_dev, const uint64_t* in_bits_dev,
                double* amps_dev) {
   if (n_shots == 0) return;
-  int maxd = 1;
-  for (int d : st.dims) maxd = std::max(maxd, d);
+  const int maxd = state_max_bond(st);
   int64_t smax = (int64_t(1) << 30) / (2 * (int64_t)maxd * 16);
   smax = std::max<int64_t>(64, std::min<int64_t>(65536, smax / 64 * 64));
   const int64_t S0 = std::min<int64_t>(smax, (int64_t)round_up((int64_t)n_shots, 64));
@@ -164,15 +190,29 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
   st.wbuf[1].ensure((size_t)S0 * 2 * maxd * sizeof(double2));
   st.part.ensure((size_t)2 * S0 * ntiles_max * sizeof(double));
   st.sel.ensure((size_t)S0);
+  ChainBuffers b;
+  b.S0 = S0;
+  b.w[0] = st.wbuf[0].as<double2>();
+  b.w[1] = st.wbuf[1].as<double2>();
+  b.part = st.part.as<double>();
+  b.sel = st.sel.as<int8_t>();
+  run_chain_with(st, b, first_shot, n_shots, seed, mode, bits_dev, log2p_dev, in_bits_dev, amps_dev);
+}
+
+void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_shot, uint64_t n_shots,
+                    uint64_t seed, int mode, uint64_t* bits_dev, double* log2p_dev,
+                    const uint64_t* in_bits_dev, double* amps_dev, bool probe) {
+  if (n_shots == 0) return;
+  const int64_t S0 = buf.S0;
   for (uint64_t b0 = 0; b0 < n_shots; b0 += (uint64_t)S0) {
     const int S = (int)std::min<uint64_t>((uint64_t)S0, n_shots - b0);
     for (int k = 0; k < st.n; ++k) {
       ChainArgs ca;
-      ca.wprev = (k == 0) ? nullptr : st.wbuf[(k - 1) & 1].as<double2>();
-      ca.sel = st.sel.as<int8_t>();
+      ca.wprev = (k == 0) ? nullptr : buf.w[(k - 1) & 1];
+      ca.sel = buf.sel;
       ca.site = st.site[k];
-      ca.wout = st.wbuf[k & 1].as<double2>();
-      ca.part = st.part.as<double>();
+      ca.wout = buf.w[k & 1];
+      ca.part = buf.part;
       ca.S = S;
       ca.dl = st.dims[k];
       ca.dr = st.dims[k + 1];
@@ -183,7 +223,7 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
         // multiply-add); HBM: site tensor + V rows read + W written
         const double fl = 16.0 * S * (double)ca.dl * ca.dr;
         const double by = 16.0 * (2.0 * ca.dl * ca.dr + (double)S * ca.dl + 2.0 * S * ca.dr);
-        Probe pr(kKcChainGemm, st.stream, fl, by);
+        Probe pr(probe ? kKcChainGemm : -1, st.stream, fl, by);
         hipExtLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, pr.start(), pr.stop(), 0, ca);
       }
       HIP_LAUNCH_OK();
@@ -197,7 +237,7 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
       da.mode = mode;
       da.seed = seed;
       da.shot0 = first_shot + b0;
-      da.sel = st.sel.as<int8_t>();
+      da.sel = buf.sel;
       da.bits = bits_dev ? bits_dev + b0 : nullptr;
       da.log2p = log2p_dev ? log2p_dev + b0 : nullptr;
       da.inbits = in_bits_dev ? in_bits_dev + b0 : nullptr;
@@ -384,3 +424,4 @@ void xeb_reduce(int n_qubits, const double* vals_dev, uint64_t m, bool is_log2, 
 }
 
 }  // namespace rcs
+

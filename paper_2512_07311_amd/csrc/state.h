@@ -39,6 +39,22 @@ struct SpectrumRecord {
   std::vector<double> values;  // descending
 };
 
+// Shape of one two-site update (always recorded; a few ints per update).
+// path: 0 full fp64 SVD, 1 randomized split accepted, 2 randomized split
+// rejected and redone with the full SVD.
+struct UpdateRecord {
+  int32_t pos, cycle, chi_l, chi_m, chi_r, kept, path;
+};
+
+// Decisions of one randomized split (learned / rsvd-at-cap modes).
+struct RsvdRecord {
+  int32_t update, pos, cycle, m, k_hat, l, k, accepted, early;
+  double eps_pred, eps_rand, outside, total;
+  float feat[66];
+  float y[32];
+  std::vector<double> values;  // projected spectrum (descending), logging builds only
+};
+
 }  // namespace rcs
 
 // Site tensor k lives in site[k] with layout [s][a][b] (physical index
@@ -64,7 +80,11 @@ struct rcs_state_s {
   int n_rsvd_early = 0;   // fall-backs decided before the projected SVD
   double log_fest = 0.0, sum_eps = 0.0;
   double build_seconds = 0.0, svd_seconds = 0.0;
+  int n_moves = 0;
+  double nominal_svd_flops = 0.0, nominal_qr_flops = 0.0;
   std::vector<rcs::SpectrumRecord> spectra;
+  std::vector<rcs::UpdateRecord> updates;
+  std::vector<rcs::RsvdRecord> rsvd_log;
   // sampler workspace (grown on demand)
   rcs::DevBuf wbuf[2], part, sel, lastp;
 };
@@ -77,9 +97,23 @@ size_t site_capacity(const rcs_state_s& st, int k);
 
 // Sampler / amplitude engine: runs the per-site shot GEMMs.
 //   mode 0: sample (bits_dev written), mode 1: amplitudes for given bits.
+// run_chain grows the state's own workspace; run_chain_with uses the given
+// buffers (S0 shots per pass) and allocates nothing.
+struct ChainBuffers {
+  double2* w[2] = {nullptr, nullptr};
+  double* part = nullptr;
+  int8_t* sel = nullptr;
+  int64_t S0 = 0;
+};
+int state_max_bond(const rcs_state_s& st);
+size_t chain_work_bytes(int64_t S, int maxd);
+ChainBuffers chain_buffers_in(char* base, int64_t S, int maxd);
 void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed, int mode,
                uint64_t* bits_dev, double* log2p_dev, const uint64_t* in_bits_dev,
                double* amps_dev);
+void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_shot, uint64_t n_shots,
+                    uint64_t seed, int mode, uint64_t* bits_dev, double* log2p_dev,
+                    const uint64_t* in_bits_dev, double* amps_dev, bool probe = true);
 
 // Shots from several states: grouped launches captured in one HIP graph.
 void run_chain_batch(rcs_state_s** states, int n, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,

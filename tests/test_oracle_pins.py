@@ -469,3 +469,99 @@ def test_sketch_entries_are_unit_phases():
     k0, k1 = philox.key_of(9)
     x0 = philox.philox4x32_10(17, 5, 3, 4, k0, k1)[0]
     assert om[17, 5] == [1, 1j, -1, -1j][int(x0) & 3]
+
+
+# ------------------------------------------------- learned-rank decisions
+# A prediction that falls by 1/4 decade per knot: y(f) = -8 f exactly
+# (knots at f = j/32 with y(0) = 0), so every crossing and every
+# interpolated value below is known in closed form.
+_Y_LINEAR = np.array([-j / 4.0 for j in range(1, 33)])
+
+
+def test_predict_rank_hand_worked_cases():
+    # crossing exactly on a knot: log10(1e-3) = -3 at f = 12/32, k = 64 * 3/8
+    assert mlp.predict_rank(_Y_LINEAR, 64, 64, 1e-3) == 24
+    # crossing between knots: -2.9 is 0.6 of the way from y_11 = -2.75 to
+    # y_12 = -3, f* = 11.6/32 = 0.3625, k = ceil(100 f*) = ceil(36.25)
+    assert mlp.predict_rank(_Y_LINEAR, 100, 100, 10 ** -2.9) == 37
+    # the cap clamps, and so does m
+    assert mlp.predict_rank(_Y_LINEAR, 100, 20, 10 ** -2.9) == 20
+    assert mlp.predict_rank(_Y_LINEAR, 7, 100, 1e-9) == 7
+    # first segment interpolates from y(0) = 0: y = -4 at f = 1/32 reaches
+    # -2 half-way, f* = 1/64; k = ceil(640 / 64) = 10, and never below 1
+    flat4 = np.full(32, -4.0)
+    assert mlp.predict_rank(flat4, 640, 640, 1e-2) == 10
+    assert mlp.predict_rank(flat4, 64, 64, 1e-2) == 1
+    # a prediction that never reaches eps keeps min(cap, m)
+    assert mlp.predict_rank(np.full(32, -1.0), 300, 128, 1e-8) == 128
+    # eps = 0 aims at 1e-20: not reached by y >= -8, so full rank
+    assert mlp.predict_rank(_Y_LINEAR, 50, 64, 0.0) == 50
+    # an exact product m f* = integer is not pushed up by rounding
+    assert mlp.predict_rank(_Y_LINEAR, 32, 32, 1e-4) == 16
+
+
+def test_predicted_eps_hand_worked_cases():
+    # on the linear prediction 10^y(k/m) = 10^(-8 k/m)
+    assert mlp.predicted_eps(_Y_LINEAR, 32, 64) == pytest.approx(1e-4, rel=1e-12)
+    assert mlp.predicted_eps(_Y_LINEAR, 64, 64) == pytest.approx(1e-8, rel=1e-12)
+    assert mlp.predicted_eps(_Y_LINEAR, 37, 100) == pytest.approx(10 ** -2.96, rel=1e-12)
+    # between knots of a non-linear prediction: plain linear interpolation
+    y = np.zeros(32)
+    y[2], y[3] = -1.0, -5.0                   # knots f = 3/32 and 4/32
+    assert mlp.predicted_eps(y, 7, 64) == pytest.approx(10 ** -3.0, rel=1e-12)   # f = 3.5/32
+    # first segment from y(0) = 0
+    assert mlp.predicted_eps(flat := np.full(32, -4.0), 1, 64) == pytest.approx(10 ** -2.0, rel=1e-12)
+    assert flat.shape == (32,)
+
+
+def test_judge_accepts_threshold_cases():
+    tau = 1e-6
+    # the threshold is max(eps, eps_pred) + tau, inclusive
+    assert rsvd.judge_accepts(1e-8 + tau, 1e-8, 0.0, tau)
+    assert not rsvd.judge_accepts(1e-8 + tau + 1e-12, 1e-8, 0.0, tau)
+    # a larger prediction raises the bar
+    assert rsvd.judge_accepts(1e-3 + tau, 1e-8, 1e-3, tau)
+    assert not rsvd.judge_accepts(1e-3 + 2 * tau, 1e-8, 1e-3, tau)
+    # tau < 0 rejects everything at or below eps as well
+    assert not rsvd.judge_accepts(0.0, 1e-8, 0.0, -1.0)
+
+
+def test_rsvd_rank_against_brute_force_search():
+    """The randomized rank rule is a minimum over k of a monotone condition:
+    checked against an exhaustive scan written from the definition."""
+    g = inputs.rng(21)
+    for trial in range(20):
+        l = int(g.integers(1, 40))
+        s = np.sort(np.abs(g.standard_normal(l)) * 10.0 ** g.uniform(-6, 0, l))[::-1]
+        outside = float(10.0 ** g.uniform(-12, -1))
+        fro2 = float(np.sum(s ** 2)) + outside
+        eps = float(10.0 ** g.uniform(-9, -1))
+        cap = int(g.integers(1, 50))
+        ok = [k for k in range(1, l + 1) if fro2 - sum(float(x) ** 2 for x in s[:k]) <= eps * fro2]
+        k_ref = min(ok[0] if ok else l, cap)
+        e_ref = (fro2 - sum(float(x) ** 2 for x in s[:k_ref])) / fro2
+        k, e = rsvd.rsvd_rank(s, fro2, cap, eps)
+        assert k == k_ref and e == pytest.approx(e_ref, rel=1e-9, abs=1e-15)
+
+
+def test_matmul_c64_rounds_inputs_per_element():
+    """complex64 emulation: inputs rounded to float32 element by element
+    (checked against Python's own IEEE single rounding through struct) and
+    products summed exactly; exact when the inputs are float32 numbers."""
+    import struct
+    g = inputs.rng(22)
+    a = g.standard_normal((5, 7)) + 1j * g.standard_normal((5, 7))
+    b = g.standard_normal((7, 4)) + 1j * g.standard_normal((7, 4))
+    f32 = lambda x: struct.unpack("f", struct.pack("f", x))[0]
+    r32 = lambda z: complex(f32(z.real), f32(z.imag))
+    ref = np.zeros((5, 4), dtype=np.complex128)
+    for i in range(5):
+        for j in range(4):
+            ref[i, j] = sum(r32(a[i, k]) * r32(b[k, j]) for k in range(7))
+    assert np.abs(precision.matmul_c64(a, b) - ref).max() < 1e-14
+    # inputs already float32: no rounding at all
+    a2 = (g.integers(-64, 64, (6, 3)) + 0.5j * g.integers(-64, 64, (6, 3))).astype(np.complex128)
+    b2 = (g.integers(-64, 64, (3, 2)) * 0.25 + 1j * g.integers(-64, 64, (3, 2))).astype(np.complex128)
+    assert np.array_equal(precision.matmul_c64(a2, b2), a2 @ b2)
+    # and the rounding is visible for values that are not float32 numbers
+    assert np.abs(precision.matmul_c64(a, b) - a @ b).max() > 0
