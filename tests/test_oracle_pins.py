@@ -215,6 +215,81 @@ def test_removed_site_mps_equals_dense():
     assert np.abs(st.to_dense() - dense.simulate(c)).max() < 1e-13
 
 
+@pytest.mark.parametrize("rows,cols,cyc,seed,removed", [(3, 4, 8, 1, None), (3, 5, 8, 2, None),
+                                                        (4, 4, 9, 3, [6]), (4, 5, 10, 4, [0, 13, 19]),
+                                                        (4, 4, 8, 5, [15])])
+def test_interleaved_network_exact_mps_equals_dense(rows, cols, cyc, seed, removed):
+    """The interleaved swap network builds the same exact state as the
+    dense simulator (which knows nothing of MPS positions): a misplaced SWAP
+    or gate, or an order left unrestored, would change the amplitudes."""
+    c = Circuit(rows, cols, cyc, seed=seed, removed=removed)
+    st = mps.build(c, 1 << (c.n // 2), 0.0, network="interleaved")
+    psi = dense.simulate(c)
+    assert st.pi == list(range(c.n))
+    assert np.abs(st.to_dense() - psi).max() <= 1e-12 * 2.0 ** (-c.n / 2)
+    assert st.canonical_residual() <= 1e-12
+
+
+def _replay_labels(circ, ops, pi0):
+    """Follow the qubit labels through a schedule: the qubit pairs every
+    fSim update acts on, per cycle, and the order at each layer's end."""
+    pi = list(pi0)
+    gates, orders = {}, {}
+    for op in ops:
+        if op[0] == "1q":
+            orders[op[2]] = list(pi)
+            continue
+        _, i, kind, t = op
+        if kind == "fsim":
+            gates.setdefault(t, []).append(tuple(sorted((pi[i], pi[i + 1]))))
+        else:
+            pi[i], pi[i + 1] = pi[i + 1], pi[i]
+        orders[t + 1] = list(pi)
+    return gates, orders
+
+
+@pytest.mark.parametrize("rows,cols,cyc,removed", [(6, 9, 14, None), (5, 6, 14, None), (4, 7, 8, [9]),
+                                                   (6, 9, 20, [40])])
+def test_interleaved_network_gates_counts_and_order(rows, cols, cyc, removed):
+    """Each cycle's fSim updates act on exactly that cycle's couplers, once
+    each; the row-major order holds at every layer boundary; on a full grid
+    the update count is the closed form: per cycle, the horizontal couplers
+    of an A/B layer, or W^2 per row pair of a C/D layer."""
+    c = Circuit(rows, cols, cyc, seed=11, removed=removed)
+    pi, ops = mps.schedule(c, "interleaved")
+    gates, orders = _replay_labels(c, ops, pi)
+    for t in range(cyc):
+        layer = sorted(tuple(sorted(e)) for e in c.layers[2 * t + 1][1])
+        assert sorted(gates.get(t, [])) == layer
+        assert orders[t + 1] == list(range(c.n))
+    n_upd = sum(1 for o in ops if o[0] == "u")
+    if removed is None:
+        W, H = c.W, c.H
+        expect = 0
+        for t in range(cyc):
+            letter = c.pattern[t % len(c.pattern)]
+            if letter == "A":
+                expect += H * (W // 2)
+            elif letter == "B":
+                expect += H * ((W - 1) // 2)
+            else:
+                pairs = len(range(0 if letter == "C" else 1, H - 1, 2))
+                expect += pairs * W * W
+        assert n_upd == expect
+    # the base network on the snake order, for comparison: 2W(W-1)+W per row pair
+    _, base_ops = mps.schedule(c, "snake")
+    assert n_upd < sum(1 for o in base_ops if o[0] == "u")
+
+
+def test_interleaved_network_53_qubit_counts():
+    """The 53-qubit, 14- and 20-cycle circuits (seed 1, one seed-chosen site
+    removed): 1,233 and 1,595 updates against 2,113 and 2,695 on the snake."""
+    for cyc, n_int, n_snake in ((14, 1233, 2113), (20, 1595, 2695)):
+        c = Circuit(6, 9, cyc, seed=1, n_removed_random=1)
+        for net, want in (("interleaved", n_int), ("snake", n_snake)):
+            assert sum(1 for o in mps.schedule(c, net)[1] if o[0] == "u") == want
+
+
 def test_single_truncation_fidelity_is_one_minus_eps():
     c = Circuit(3, 4, 8, seed=3)
     psi = dense.simulate(c)
