@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--form", default="both", choices=["plain", "learned", "both"])
     ap.add_argument("--mlp", default=None, help=".npy packed network weights (learned form)")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--network", default="interleaved", choices=["interleaved", "snake"],
+                    help="MPS order and swap network of the schedule")
     ap.add_argument("--profile-every", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-ops", type=int, default=-1, help="truncate the schedule (debugging only)")
@@ -280,7 +282,7 @@ def main():
         return main_batch(args, wl)
     shots = args.shots or wl["shots"]
     circ = rcs.Circuit(wl["rows"], wl["cols"], wl["cycles"], args.seed,
-                       n_removed_random=wl["removed_random"])
+                       n_removed_random=wl["removed_random"], network=args.network)
     stream = torch.cuda.current_stream()
     bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
     log2p = torch.zeros(shots, dtype=torch.float64, device="cuda")
@@ -291,7 +293,7 @@ def main():
     # ---- warm-up on the 30-qubit chi-256 circuit (every kernel class); its
     # logged spectra are the rank network's training data
     tr = inputs.WORKLOADS["rcs30_5x6_c14_chi256"]
-    tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1)
+    tc = rcs.Circuit(tr["rows"], tr["cols"], tr["cycles"], args.seed + 1, network=args.network)
     n_warm = 0
     mlp_w = None
     if args.warmup > 0 or (run_learned and not args.mlp):
@@ -366,6 +368,7 @@ def main():
         "data": "synthetic (seeded random circuit)",
         "config": {"workload": args.workload, "qubits": circ.n, "cycles": wl["cycles"], "chi": wl["chi"],
                    "eps": wl["eps"], "shots": shots, "form": "plain" if run_plain else "learned",
+                   "swap_network": args.network,
                    "contraction": main_kw["contraction"], "circuit_seed": args.seed, "max_ops": args.max_ops,
                    "warmup_workload": "rcs30_5x6_c14_chi256" if n_warm else None},
         "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},

@@ -73,6 +73,8 @@ typedef struct {
   const char* pattern;            /* letters from "ABCD"; NULL -> "ABCDCDAB"  */
   double theta, phi;              /* fSim angles (pi/2, pi/6 for Sycamore)    */
   int32_t final_1q_layer;         /* 1: one more single-qubit layer at end    */
+  int32_t swap_network;           /* MPS order and swap network (0 or 1):     */
+                                  /* 0 snake, 1 interleaved row pairs         */
 } rcs_circuit_desc;
 
 /* Validates and generates the circuit and its MPS schedule (host only, no
@@ -91,10 +93,18 @@ rcs_status rcs_circuit_info(rcs_circuit c, int32_t* n_qubits, int32_t* n_layers_
 rcs_status rcs_circuit_one_qubit_gates(rcs_circuit c, int32_t* gates_host);
 
 /* The compiled MPS schedule.  snake_host[pos] = qubit at MPS position pos
- * (boustrophedon order, rows along the short side).  ops_host[4*o + 0..3] =
- * {kind, arg, gate, cycle}: kind 0 = single-qubit layer (arg = layer index),
- * kind 1 = two-site update at positions (arg, arg+1) with gate 0 = fSim,
- * 1 = SWAP.  Vertical couplers become SWAP chains around the fSim update.
+ * before the first op.  ops_host[4*o + 0..3] = {kind, arg, gate, cycle}:
+ * kind 0 = single-qubit layer (arg = layer index), kind 1 = two-site update
+ * at positions (arg, arg+1) with gate 0 = fSim, 1 = SWAP (a SWAP update also
+ * exchanges the two positions' qubits).  Networks (rcs_circuit_desc.
+ * swap_network; rows run along the short side in both):
+ *   0 snake: boustrophedon order; a vertical coupler at positions i < j is a
+ *     SWAP chain j-1..i+1, the fSim at i, and the chain back i+1..j-1;
+ *   1 interleaved: row-major order (qubit q at position q between layers);
+ *     each row pair of a vertical layer is sorted into column-interleaved
+ *     order by insertion (bottom qubits walk left past larger keys 2c / 2c+1,
+ *     the column's fSim follows each walk), then the SWAPs are replayed in
+ *     reverse.  W^2 updates per full row pair instead of 2W(W-1) + W.
  * Capacities: n_qubits and 4 * n_ops. */
 rcs_status rcs_circuit_schedule(rcs_circuit c, int32_t* snake_host, int32_t* ops_host);
 

@@ -10,9 +10,20 @@
 //   * gate draw for qubit q at layer t: x = word x of Philox(seed; (q,t,0,0));
 //     t = 0: floor(3x / 2^32); t > 0: the two gates other than the previous
 //     one, in increasing order, indexed by x >> 31.
-// Schedule (snake-ordered MPS): positions follow rows, even rows left to
-// right, odd rows right to left; a gate on positions i < j becomes SWAP
-// updates at j-1..i+1, the gate update at i, SWAP updates at i+1..j-1.
+// Schedules:
+//  * snake (network 0): positions follow rows, even rows left to right, odd
+//    rows right to left; a gate on positions i < j becomes SWAP updates at
+//    j-1..i+1, the gate update at i, SWAP updates at i+1..j-1;
+//  * interleaved (network 1): positions follow rows, every row left to
+//    right, so position = qubit number between layers.  A horizontal gate
+//    is one update.  A vertical layer handles its row pairs (r, r+1) in
+//    order: the pair's block (row r then row r+1) is put in the order of
+//    the key 2c (top, column c) / 2c+1 (bottom) by insertion -- bottom
+//    qubits in column order walk left by SWAP updates while the left
+//    neighbour's key is larger, and a column's fSim update follows as soon
+//    as its walk stops beside the top partner -- and the walk's SWAPs are
+//    then replayed last-first to restore the row-major order.  A full row
+//    pair is W^2 updates instead of the snake's 2W(W-1) + W.
 #include "circuit.h"
 
 #include <algorithm>
@@ -67,6 +78,74 @@ static std::vector<int> draw_layer(uint64_t seed, int n, int t, const std::vecto
   return out;
 }
 
+// Interleaved network (see the file header).  `order` tracks which qubit
+// sits at each position while a row pair is being sorted.
+static void compile_interleaved(rcs_circuit_s& c) {
+  const int n = c.n;
+  std::vector<int> order(n);
+  for (int p = 0; p < n; ++p) order[p] = p;      // row-major numbering
+  c.snake = order;
+  // column and row of every qubit
+  std::vector<int> col_of(n), row_of(n);
+  for (int s = 0; s < c.W * c.H; ++s)
+    if (c.qubit_of_site[s] >= 0) {
+      col_of[c.qubit_of_site[s]] = s % c.W;
+      row_of[c.qubit_of_site[s]] = s / c.W;
+    }
+  for (int t = 0; t < c.n_cycles; ++t) {
+    c.ops.push_back(Op{0, t, 0, t});
+    const char letter = c.pattern[t % c.pattern.size()];
+    const auto& cp = c.layers_2q[t];
+    if (letter == 'A' || letter == 'B') {
+      std::vector<int> left;
+      for (auto& e : cp) {
+        const int a = std::min(e.first, e.second), b = std::max(e.first, e.second);
+        RCS_REQUIRE(b == a + 1, "horizontal coupler not on neighbouring positions");
+        left.push_back(a);
+      }
+      std::sort(left.begin(), left.end());
+      for (int a : left) c.ops.push_back(Op{1, a, 0, t});
+      continue;
+    }
+    // vertical: top qubit -> bottom partner of this layer's couplers
+    std::vector<int> partner_above(n, -1);
+    for (auto& e : cp) {
+      const int a = std::min(e.first, e.second), b = std::max(e.first, e.second);
+      partner_above[b] = a;
+    }
+    for (int r = (letter == 'C' ? 0 : 1); r + 1 < c.H; r += 2) {
+      // block [lo, hi): the present qubits of rows r and r+1 (contiguous)
+      int lo = n, hi = 0;
+      for (int q = 0; q < n; ++q)
+        if (row_of[q] == r || row_of[q] == r + 1) {
+          lo = std::min(lo, q);
+          hi = std::max(hi, q + 1);
+        }
+      if (lo >= hi) continue;
+      auto key = [&](int q) { return 2 * col_of[q] + (row_of[q] == r + 1 ? 1 : 0); };
+      std::vector<int> walk;                      // SWAP positions, in order
+      for (int q = lo; q < hi; ++q) {
+        if (row_of[q] != r + 1) continue;         // bottom qubits, column order
+        int p = (int)(std::find(order.begin() + lo, order.begin() + hi, q) - order.begin());
+        while (p > lo && key(order[p - 1]) > key(q)) {
+          c.ops.push_back(Op{1, p - 1, 1, t});
+          walk.push_back(p - 1);
+          std::swap(order[p - 1], order[p]);
+          --p;
+        }
+        if (p > lo && partner_above[q] >= 0 && order[p - 1] == partner_above[q])
+          c.ops.push_back(Op{1, p - 1, 0, t});
+      }
+      for (auto it = walk.rbegin(); it != walk.rend(); ++it) {
+        c.ops.push_back(Op{1, *it, 1, t});
+        std::swap(order[*it], order[*it + 1]);
+      }
+    }
+    for (int p = 0; p < n; ++p) RCS_REQUIRE(order[p] == p, "interleaved network did not restore the order");
+  }
+  if (c.final_layer) c.ops.push_back(Op{0, c.n_cycles, 0, c.n_cycles});
+}
+
 void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
   RCS_REQUIRE(d.rows >= 2 && d.cols >= 2, "grid must be at least 2x2");
   RCS_REQUIRE((int64_t)d.rows * d.cols <= 4096, "grid too large");
@@ -74,6 +153,7 @@ void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
   RCS_REQUIRE(d.n_removed >= 0 && (d.n_removed == 0 || d.removed_sites), "bad removed sites");
   RCS_REQUIRE(d.n_removed_random == 0 || d.n_removed_random == 1,
               "n_removed_random must be 0 or 1");
+  RCS_REQUIRE(d.swap_network == 0 || d.swap_network == 1, "swap_network must be 0 or 1");
   c.rows = d.rows;
   c.cols = d.cols;
   c.W = std::min(d.rows, d.cols);
@@ -140,6 +220,14 @@ void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
   }
   if (c.final_layer) c.layers_1q.push_back(draw_layer(c.seed, n, c.n_cycles, prev));
 
+  c.ops.clear();
+  c.n_updates = 0;
+  c.network = d.swap_network;
+  if (c.network == 1) {
+    compile_interleaved(c);
+    for (auto& o : c.ops) c.n_updates += (o.kind == 1);
+    return;
+  }
   // snake order and schedule
   c.snake.clear();
   for (int r = 0; r < c.H; ++r)
@@ -150,8 +238,6 @@ void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
     }
   std::vector<int> pos(n);
   for (int p = 0; p < n; ++p) pos[c.snake[p]] = p;
-  c.ops.clear();
-  c.n_updates = 0;
   for (int t = 0; t < c.n_cycles; ++t) {
     c.ops.push_back(Op{0, t, 0, t});
     std::vector<std::pair<int, int>> pr;

@@ -28,7 +28,8 @@ struct rcs_circuit_s {
   int n = 0;
   std::vector<std::vector<int>> layers_1q;               // gate index per qubit
   std::vector<std::vector<std::pair<int, int>>> layers_2q; // couplers (qubit ids)
-  std::vector<int> snake;              // position -> qubit
+  int network = 0;                     // 0 snake, 1 interleaved row pairs
+  std::vector<int> snake;              // position -> qubit at the start
   std::vector<Op> ops;
   int n_updates = 0;
   std::array<cplx, 16> fsim;           // row-major 4x4 in |s1 s2>, index 2 s1 + s2

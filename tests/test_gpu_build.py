@@ -61,6 +61,43 @@ def test_truncated_build_matches_oracle(env, rows, cols, cyc, seed, chi, eps):
     assert inf.n_truncations == c.n_updates
 
 
+@pytest.mark.parametrize("rows,cols,cyc,seed,removed", [(3, 4, 8, 1, ()), (4, 4, 8, 2, ()),
+                                                        (4, 5, 9, 3, (7,)), (5, 4, 10, 4, (0, 13))])
+def test_interleaved_exact_build_equals_dense(env, rows, cols, cyc, seed, removed):
+    """The interleaved swap network on the GPU: exact builds equal the dense
+    state to 1e-10 2^(-n/2) elementwise, with the oracle's bond dimensions."""
+    rcs, torch = env
+    c = rcs.Circuit(rows, cols, cyc, seed, removed=removed, network="interleaved")
+    oc1 = oc.Circuit(rows, cols, cyc, seed, removed=list(removed) or None)
+    g = rcs.State.build(c, 1024, 0.0)
+    psi = dense.simulate(oc1)
+    got = _amps(torch, g, np.arange(1 << c.n))
+    assert np.abs(got - psi).max() <= 1e-10 * 2.0 ** (-c.n / 2)
+    om = mps.build(oc1, 1024, 0.0, network="interleaved")
+    assert list(g.layout()[0]) == om.bond_dims()
+    assert list(g.to_host()[1]) == list(range(c.n))
+
+
+@pytest.mark.parametrize("rows,cols,cyc,seed,removed,chi,eps", [(4, 5, 10, 3, (), 16, 1e-10),
+                                                                (3, 7, 14, 8, (), 33, 1e-9),
+                                                                (5, 4, 12, 4, (0,), 12, 1e-8)])
+def test_interleaved_truncated_build_matches_oracle(env, rows, cols, cyc, seed, removed, chi, eps):
+    """Truncated builds on the interleaved network against the oracle on the
+    same schedule: amplitudes within the cut-conditioning bar, equal bond
+    dimensions, estimated fidelity to 1e-6 relative."""
+    rcs, torch = env
+    c = rcs.Circuit(rows, cols, cyc, seed, removed=removed, network="interleaved")
+    om = mps.build(oc.Circuit(rows, cols, cyc, seed, removed=list(removed) or None), chi, eps,
+                   network="interleaved")
+    g = rcs.State.build(c, chi, eps)
+    b = inputs.random_bitstrings(c.n, 1000, seed=25)
+    assert normwise_rel(_amps(torch, g, b), om.amplitudes(b)) < truncated_tolerance(om)
+    inf = g.info()
+    assert abs(inf.log_fidelity_est - om.log_fest) <= 1e-6 * max(1e-300, abs(om.log_fest)) + 1e-14
+    assert list(g.layout()[0]) == om.bond_dims()
+    assert inf.n_truncations == c.n_updates
+
+
 def test_shots_from_built_state(env):
     rcs, torch = env
     c = rcs.Circuit(4, 5, 10, 11)

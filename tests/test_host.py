@@ -38,15 +38,16 @@ def test_exports_every_declared_symbol(rcs):
 CONFIGS = [(3, 4, 8, 0), (5, 6, 14, 0), (6, 9, 14, 1), (6, 9, 20, 1), (4, 5, 3, 0), (2, 7, 9, 0)]
 
 
+@pytest.mark.parametrize("network", ["snake", "interleaved"])
 @pytest.mark.parametrize("rows,cols,cyc,rr", CONFIGS)
 @pytest.mark.parametrize("seed", [1, 2, 12345678901234])
-def test_generator_and_schedule_match_oracle(rcs, rows, cols, cyc, rr, seed):
-    c = rcs.Circuit(rows, cols, cyc, seed, n_removed_random=rr)
+def test_generator_and_schedule_match_oracle(rcs, rows, cols, cyc, rr, seed, network):
+    c = rcs.Circuit(rows, cols, cyc, seed, n_removed_random=rr, network=network)
     o = OCircuit(rows, cols, cyc, seed, n_removed_random=rr)
     assert c.n == o.n
     assert np.array_equal(c.one_qubit_gates(), o.one_qubit_draws())
     snake, ops = c.schedule()
-    pi, oops = omps.schedule(o)
+    pi, oops = omps.schedule(o, network)
     assert list(snake) == pi
     ref = []
     for op in oops:
@@ -62,17 +63,29 @@ def test_generator_and_schedule_match_oracle(rcs, rows, cols, cyc, rr, seed):
     assert c.n_updates == sum(1 for r in ref if r[0] == 1)
 
 
-def test_explicit_removed_sites_and_pattern(rcs):
-    c = rcs.Circuit(4, 5, 6, 9, pattern="ACBD", removed=[0, 7])
+@pytest.mark.parametrize("network", ["snake", "interleaved"])
+def test_explicit_removed_sites_and_pattern(rcs, network):
+    c = rcs.Circuit(4, 5, 6, 9, pattern="ACBD", removed=[0, 7], network=network)
     o = OCircuit(4, 5, 6, 9, pattern="ACBD", removed=[0, 7])
     assert c.n == o.n == 18
     assert np.array_equal(c.one_qubit_gates(), o.one_qubit_draws())
-    assert list(c.schedule()[0]) == omps.schedule(o)[0]
+    snake, ops = c.schedule()
+    pi, oops = omps.schedule(o, network)
+    assert list(snake) == pi
+    assert [tuple(x[1:3]) for x in ops if x[0] == 1] == \
+        [(op[1], 0 if op[2] == "fsim" else 1) for op in oops if op[0] == "u"]
 
 
 def test_c3_update_count(rcs):
     c = rcs.Circuit(6, 9, 14, 1, n_removed_random=1)
     assert c.n == 53 and c.n_updates == 2113
+    c = rcs.Circuit(6, 9, 14, 1, n_removed_random=1, network="interleaved")
+    assert c.n == 53 and c.n_updates == 1233
+
+
+def test_invalid_network(rcs):
+    with pytest.raises(KeyError):
+        rcs.Circuit(3, 3, 2, 1, network="ladder")
 
 
 @pytest.mark.parametrize("kw,msg", [
