@@ -163,6 +163,24 @@ rcs_status rcs_sample(rcs_state s, uint64_t n_shots, uint64_t seed, uint64_t* bi
 rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
                             uint64_t* bits_dev, double* log2p_dev);
 
+/* Allocation-free form of rcs_sample_range, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same shots, bit
+ * for bit.  The sampler's workspace (two W row buffers, per-shot partial
+ * norms and chosen branches) lives in a static 64 MiB device array that the
+ * library holds on every GPU it runs on until the process ends; no device
+ * memory is allocated or freed by the call, and no library routine that
+ * allocates is called.  Shots run in passes of the largest multiple of 64
+ * (at most 65,536) whose workspace fits the array: 960 shots at maximum
+ * bond 1024, 448 at 2048.  All calls on one GPU share the array, so calls
+ * that overlap on one GPU (other streams or threads) race; calls on one
+ * stream are ordered and safe.  Errors: as rcs_sample_range, plus
+ * INVALID_ARG when the state's maximum bond needs more than the array for a
+ * 64-shot pass (bond above 16,320), DEVICE when the array's address cannot
+ * be obtained. */
+rcs_status rcs_sample_range_noalloc(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                                    uint64_t* bits_dev, double* log2p_dev);
+
 /* Shots from n states in one launch sequence: shot j of state i goes to
  * bits_dev[i * n_shots + j] (and log2p_dev likewise, nullable); identical to
  * rcs_sample on each state.  Per site index one grouped GEMM launch covers

@@ -79,6 +79,7 @@ _SIGS = {
     "rcs_build_batch": [_P(_vp), _P(_i32), _P(_d), _i32, _P(BuildOpts), _P(_vp)],
     "rcs_sample": [_vp, _u64, _u64, _vp, _vp],
     "rcs_sample_range": [_vp, _u64, _u64, _u64, _vp, _vp],
+    "rcs_sample_range_noalloc": [_vp, _u64, _u64, _u64, _vp, _vp],
     "rcs_sample_batch": [_P(_vp), _i32, _u64, _u64, _vp, _vp],
     "rcs_amplitudes": [_vp, _vp, _u64, _vp],
     "rcs_xeb": [_i32, _vp, _u64, _P(_d), _P(_d)],
@@ -342,6 +343,13 @@ class State:
         n_shots = bits.numel() if n_shots is None else n_shots
         _check(_lib.rcs_sample_range(self.h, first_shot, n_shots, seed & 0xFFFFFFFFFFFFFFFF,
                                      _ptr(bits), _ptr(log2p)))
+
+    def sample_noalloc(self, bits, log2p=None, n_shots=None, seed=0, first_shot=0):
+        """As sample(), through the allocation-free entry point (the library's
+        static per-device scratch array instead of allocated workspace)."""
+        n_shots = bits.numel() if n_shots is None else n_shots
+        _check(_lib.rcs_sample_range_noalloc(self.h, first_shot, n_shots, seed & 0xFFFFFFFFFFFFFFFF,
+                                             _ptr(bits), _ptr(log2p)))
 
     def amplitudes(self, bits, amps):
         """amps: float64 device tensor (m, 2) or complex128 (m,)."""

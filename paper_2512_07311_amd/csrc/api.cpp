@@ -304,6 +304,16 @@ rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, 
   RCS_API_END
 }
 
+rcs_status rcs_sample_range_noalloc(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                                    uint64_t* bits_dev, double* log2p_dev) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s, "null state");
+  RCS_REQUIRE(bits_dev || n_shots == 0, "null bits_dev");
+  if (!s->canonical) rcs::fail(RCS_ERR_STATE, "rcs_sample_range_noalloc: state is not right-canonical");
+  rcs::run_chain_noalloc(*s, first_shot, n_shots, seed, bits_dev, log2p_dev);
+  RCS_API_END
+}
+
 rcs_status rcs_sample(rcs_state s, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
                       double* log2p_dev) {
   return rcs_sample_range(s, 0, n_shots, seed, bits_dev, log2p_dev);

@@ -10,6 +10,8 @@
 // the branch and records the bit.  The next site reads its V rows straight
 // out of W at the chosen half (no copy).  The last site has a single column,
 // whose |w|^2 is p(b).
+#include <mutex>
+
 #include "gemm_f64.h"
 #include "prof.h"
 #include "state.h"
@@ -247,6 +249,64 @@ void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_sho
       HIP_LAUNCH_OK();
     }
   }
+}
+
+// ------------------------------------------------ allocation-free sampling
+// Workspace for callers that cannot allocate device memory: one statically
+// sized device array, of which every GPU the library runs on holds its own
+// copy until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name is
+// not a device address in host code).  Nothing in it has to start at zero:
+// every pass writes the partial norms, the chosen branches and the W rows it
+// later reads.  All calls on one GPU share the array, so calls that overlap
+// on one GPU (two streams, two threads) race.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device
+// with that device current.
+static char* scratch_on(int dev) {
+  RCS_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != dev) HIP_OK(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) HIP_OK(hipSetDevice(cur));
+    HIP_OK(e);
+    RCS_REQUIRE(ptr != nullptr, "no device address for the sampler scratch");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+// Largest shot pass (a multiple of 64, at most 65,536) whose workspace fits
+// the scratch array at maximum bond maxd; 0 when not even 64 shots fit.
+int64_t noalloc_pass_shots(int maxd) {
+  int64_t S = 65536;
+  while (S >= 64 && chain_work_bytes(S, maxd) > kNoAllocScratchBytes) S -= 64;
+  return S >= 64 ? S : 0;
+}
+
+void run_chain_noalloc(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                       uint64_t* bits_dev, double* log2p_dev) {
+  const int maxd = state_max_bond(st);
+  const int64_t smax = noalloc_pass_shots(maxd);
+  if (smax == 0)
+    fail(RCS_ERR_INVALID_ARG, "state's bond dimension too large for the allocation-free sampler's scratch");
+  char* base = scratch_on(st.device);
+  if (n_shots == 0) return;
+  const int64_t S0 = std::min<int64_t>(smax, (int64_t)round_up((int64_t)n_shots, 64));
+  const ChainBuffers b = chain_buffers_in(base, S0, maxd);
+  run_chain_with(st, b, first_shot, n_shots, seed, 0, bits_dev, log2p_dev, nullptr, nullptr, false);
 }
 
 // Batched sampling: for every shot pass and site index, one grouped GEMM

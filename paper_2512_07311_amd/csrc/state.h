@@ -115,6 +115,13 @@ void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_sho
                     uint64_t seed, int mode, uint64_t* bits_dev, double* log2p_dev,
                     const uint64_t* in_bits_dev, double* amps_dev, bool probe = true);
 
+// Same shots as run_chain (mode 0) with the workspace in the library's
+// static per-device scratch array: no device allocation.
+void run_chain_noalloc(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
+                       uint64_t* bits_dev, double* log2p_dev);
+size_t noalloc_scratch_bytes();
+int64_t noalloc_pass_shots(int maxd);
+
 // Shots from several states: grouped launches captured in one HIP graph.
 void run_chain_batch(rcs_state_s** states, int n, uint64_t n_shots, uint64_t seed, uint64_t* bits_dev,
                      double* log2p_dev, hipStream_t user_stream);
