@@ -19,11 +19,14 @@ step below is the plain textbook operation, in complex128 with numpy/LAPACK:
   Horizontal couplers join neighbouring positions.  For a vertical layer,
   each row pair (r, r+1) of the pattern sits in one contiguous block (row r,
   then row r+1).  The block is sorted by the key 2c for the top qubit of
-  column c and 2c+1 for the bottom one, by insertion: bottom qubits in
-  column order each move left by SWAP updates past every larger key, and the
-  fSim update of a column follows as soon as its bottom qubit stops next to
-  its top partner.  The recorded SWAPs are then replayed in reverse order,
-  which restores the row-major order.  A full row pair costs W^2 updates
+  column c and 2c+1 for the bottom one, by insertion, and the fSim update of
+  a column follows as soon as the moving qubit stops next to its partner.
+  The recorded SWAPs are then replayed in reverse order, which restores the
+  row-major order.  Cycles alternate direction so that each layer starts
+  where the previous one left the orthogonality centre: even cycles take
+  their gates and row pairs left to right and sort by moving bottom qubits
+  left (in column order); odd cycles go right to left and move top qubits
+  right (in reverse column order).  A full row pair costs W^2 updates
   (W(W-1)/2 SWAPs each way plus W gates) against 2W(W-1) + W for the base
   network on the snake order;
 * update(i, G): move the orthogonality centre into {i, i+1} with exact QR/LQ
@@ -99,16 +102,20 @@ def _schedule_interleaved(circ):
             ops.append(("1q", data, t))
             continue
         letter = circ.pattern[t % len(circ.pattern)]
+        right_to_left = (t % 2 == 1)
         if letter in "AB":
             # horizontal neighbours are neighbouring positions
-            for a, b in sorted(data):
+            for a, b in sorted(data, reverse=right_to_left):
                 i, j = sorted((pi.index(a), pi.index(b)))
                 assert j == i + 1
                 ops.append(("u", i, "fsim", t))
         else:
             coupled = set(data)
             first_row = 0 if letter == "C" else 1
-            for r in range(first_row, circ.H - 1, 2):
+            row_pairs = list(range(first_row, circ.H - 1, 2))
+            if right_to_left:
+                row_pairs.reverse()
+            for r in row_pairs:
                 top = [circ.qubit_of_site[circ.site(r, c)] for c in range(circ.W)
                        if circ.site(r, c) in circ.qubit_of_site]
                 bot = [circ.qubit_of_site[circ.site(r + 1, c)] for c in range(circ.W)
@@ -118,18 +125,29 @@ def _schedule_interleaved(circ):
                     key[q] = 2 * (circ.present[q] % circ.W)
                 for q in bot:
                     key[q] = 2 * (circ.present[q] % circ.W) + 1
-                start = min(pi.index(q) for q in top + bot)
+                block = [pi.index(q) for q in top + bot]
+                start, end = min(block), max(block)
                 swaps = []
-                for q in bot:                        # column order
-                    p = pi.index(q)
-                    while p > start and key[pi[p - 1]] > key[q]:
-                        ops.append(("u", p - 1, "swap", t))
-                        swaps.append(p - 1)
-                        pi[p - 1], pi[p] = pi[p], pi[p - 1]
-                        p -= 1
-                    above = pi[p - 1] if p > start else None
-                    if above is not None and (above, q) in coupled:
-                        ops.append(("u", p - 1, "fsim", t))
+                if not right_to_left:
+                    for q in bot:                        # column order
+                        p = pi.index(q)
+                        while p > start and key[pi[p - 1]] > key[q]:
+                            ops.append(("u", p - 1, "swap", t))
+                            swaps.append(p - 1)
+                            pi[p - 1], pi[p] = pi[p], pi[p - 1]
+                            p -= 1
+                        if p > start and (pi[p - 1], q) in coupled:
+                            ops.append(("u", p - 1, "fsim", t))
+                else:
+                    for q in reversed(top):              # reverse column order
+                        p = pi.index(q)
+                        while p < end and key[pi[p + 1]] < key[q]:
+                            ops.append(("u", p, "swap", t))
+                            swaps.append(p)
+                            pi[p], pi[p + 1] = pi[p + 1], pi[p]
+                            p += 1
+                        if p < end and (q, pi[p + 1]) in coupled:
+                            ops.append(("u", p, "fsim", t))
                 for k in reversed(swaps):
                     ops.append(("u", k, "swap", t))
                     pi[k], pi[k + 1] = pi[k + 1], pi[k]

@@ -262,6 +262,11 @@ def test_interleaved_network_gates_counts_and_order(rows, cols, cyc, removed):
         layer = sorted(tuple(sorted(e)) for e in c.layers[2 * t + 1][1])
         assert sorted(gates.get(t, [])) == layer
         assert orders[t + 1] == list(range(c.n))
+        # layers alternate direction: the first update of an odd cycle lies
+        # right of its last one, the reverse for an even cycle
+        pos = [o[1] for o in ops if o[0] == "u" and o[3] == t]
+        if len(pos) > 1:
+            assert (pos[0] > pos[-1]) if t % 2 else (pos[0] < pos[-1])
     n_upd = sum(1 for o in ops if o[0] == "u")
     if removed is None:
         W, H = c.W, c.H
