@@ -102,9 +102,11 @@ rcs_status rcs_circuit_one_qubit_gates(rcs_circuit c, int32_t* gates_host);
  *     SWAP chain j-1..i+1, the fSim at i, and the chain back i+1..j-1;
  *   1 interleaved: row-major order (qubit q at position q between layers);
  *     each row pair of a vertical layer is sorted into column-interleaved
- *     order by insertion (bottom qubits walk left past larger keys 2c / 2c+1,
- *     the column's fSim follows each walk), then the SWAPs are replayed in
- *     reverse.  W^2 updates per full row pair instead of 2W(W-1) + W.
+ *     order by insertion (keys 2c top / 2c+1 bottom; the column's fSim
+ *     follows each walk), then the SWAPs are replayed in reverse.  Even
+ *     cycles run left to right (bottom qubits walk left), odd cycles right
+ *     to left (top qubits walk right).  W^2 updates per full row pair
+ *     instead of 2W(W-1) + W.
  * Capacities: n_qubits and 4 * n_ops. */
 rcs_status rcs_circuit_schedule(rcs_circuit c, int32_t* snake_host, int32_t* ops_host);
 

@@ -16,14 +16,18 @@
 //    j-1..i+1, the gate update at i, SWAP updates at i+1..j-1;
 //  * interleaved (network 1): positions follow rows, every row left to
 //    right, so position = qubit number between layers.  A horizontal gate
-//    is one update.  A vertical layer handles its row pairs (r, r+1) in
-//    order: the pair's block (row r then row r+1) is put in the order of
-//    the key 2c (top, column c) / 2c+1 (bottom) by insertion -- bottom
-//    qubits in column order walk left by SWAP updates while the left
-//    neighbour's key is larger, and a column's fSim update follows as soon
-//    as its walk stops beside the top partner -- and the walk's SWAPs are
-//    then replayed last-first to restore the row-major order.  A full row
-//    pair is W^2 updates instead of the snake's 2W(W-1) + W.
+//    is one update.  A vertical layer handles its row pairs (r, r+1) one at
+//    a time: the pair's block (row r then row r+1) is put in the order of
+//    the key 2c (top, column c) / 2c+1 (bottom) by insertion, a column's
+//    fSim update following as soon as the walking qubit stops beside its
+//    partner, and the walk's SWAPs are then replayed last-first to restore
+//    the row-major order.  Even cycles run left to right (gates and row
+//    pairs in increasing position; bottom qubits, in column order, walk
+//    left while the left neighbour's key is larger); odd cycles run right to
+//    left (decreasing position; top qubits, in reverse column order, walk
+//    right while the right neighbour's key is smaller), so each layer
+//    starts where the orthogonality centre was left.  A full row pair is
+//    W^2 updates instead of the snake's 2W(W-1) + W.
 #include "circuit.h"
 
 #include <algorithm>
@@ -95,6 +99,7 @@ static void compile_interleaved(rcs_circuit_s& c) {
   for (int t = 0; t < c.n_cycles; ++t) {
     c.ops.push_back(Op{0, t, 0, t});
     const char letter = c.pattern[t % c.pattern.size()];
+    const bool leftward = (t % 2) == 1;     // odd cycles run right to left
     const auto& cp = c.layers_2q[t];
     if (letter == 'A' || letter == 'B') {
       std::vector<int> left;
@@ -104,6 +109,7 @@ static void compile_interleaved(rcs_circuit_s& c) {
         left.push_back(a);
       }
       std::sort(left.begin(), left.end());
+      if (leftward) std::reverse(left.begin(), left.end());
       for (int a : left) c.ops.push_back(Op{1, a, 0, t});
       continue;
     }
@@ -113,7 +119,10 @@ static void compile_interleaved(rcs_circuit_s& c) {
       const int a = std::min(e.first, e.second), b = std::max(e.first, e.second);
       partner_above[b] = a;
     }
-    for (int r = (letter == 'C' ? 0 : 1); r + 1 < c.H; r += 2) {
+    std::vector<int> row_pairs;
+    for (int r = (letter == 'C' ? 0 : 1); r + 1 < c.H; r += 2) row_pairs.push_back(r);
+    if (leftward) std::reverse(row_pairs.begin(), row_pairs.end());
+    for (int r : row_pairs) {
       // block [lo, hi): the present qubits of rows r and r+1 (contiguous)
       int lo = n, hi = 0;
       for (int q = 0; q < n; ++q)
@@ -124,17 +133,32 @@ static void compile_interleaved(rcs_circuit_s& c) {
       if (lo >= hi) continue;
       auto key = [&](int q) { return 2 * col_of[q] + (row_of[q] == r + 1 ? 1 : 0); };
       std::vector<int> walk;                      // SWAP positions, in order
-      for (int q = lo; q < hi; ++q) {
-        if (row_of[q] != r + 1) continue;         // bottom qubits, column order
-        int p = (int)(std::find(order.begin() + lo, order.begin() + hi, q) - order.begin());
-        while (p > lo && key(order[p - 1]) > key(q)) {
-          c.ops.push_back(Op{1, p - 1, 1, t});
-          walk.push_back(p - 1);
-          std::swap(order[p - 1], order[p]);
-          --p;
+      auto where = [&](int q) { return (int)(std::find(order.begin() + lo, order.begin() + hi, q) - order.begin()); };
+      if (!leftward) {
+        for (int q = lo; q < hi; ++q) {
+          if (row_of[q] != r + 1) continue;       // bottom qubits, column order
+          int p = where(q);
+          while (p > lo && key(order[p - 1]) > key(q)) {
+            c.ops.push_back(Op{1, p - 1, 1, t});
+            walk.push_back(p - 1);
+            std::swap(order[p - 1], order[p]);
+            --p;
+          }
+          if (p > lo && partner_above[q] >= 0 && order[p - 1] == partner_above[q])
+            c.ops.push_back(Op{1, p - 1, 0, t});
         }
-        if (p > lo && partner_above[q] >= 0 && order[p - 1] == partner_above[q])
-          c.ops.push_back(Op{1, p - 1, 0, t});
+      } else {
+        for (int q = hi - 1; q >= lo; --q) {
+          if (row_of[q] != r) continue;           // top qubits, reverse column order
+          int p = where(q);
+          while (p + 1 < hi && key(order[p + 1]) < key(q)) {
+            c.ops.push_back(Op{1, p, 1, t});
+            walk.push_back(p);
+            std::swap(order[p], order[p + 1]);
+            ++p;
+          }
+          if (p + 1 < hi && partner_above[order[p + 1]] == q) c.ops.push_back(Op{1, p, 0, t});
+        }
       }
       for (auto it = walk.rbegin(); it != walk.rend(); ++it) {
         c.ops.push_back(Op{1, *it, 1, t});
