@@ -226,6 +226,9 @@ typedef struct {
   double nominal_svd_flops;/* sum over full SVDs of 4 (14 m n^2 + 8 n^3),    */
                            /* m >= n the two-site matrix shape              */
   double nominal_qr_flops; /* sum over centre moves of 4 (2 m n^2 - 2n^3/3) */
+  int32_t n_precond;       /* full SVDs done on the Cholesky-preconditioned */
+                           /* matrix (Jacobi on R^H, R^H R = X^H X)         */
+  int32_t n_precond_fallback; /* preconditioned attempts redone on X itself */
 } rcs_state_info;
 
 rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out);

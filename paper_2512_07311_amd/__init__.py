@@ -64,7 +64,8 @@ class StateInfo(C.Structure):
                 ("sum_eps", C.c_double), ("build_seconds", C.c_double),
                 ("svd_seconds", C.c_double), ("device_bytes", C.c_int64),
                 ("n_center_moves", C.c_int32), ("nominal_svd_flops", C.c_double),
-                ("nominal_qr_flops", C.c_double)]
+                ("nominal_qr_flops", C.c_double), ("n_precond", C.c_int32),
+                ("n_precond_fallback", C.c_int32)]
 
 
 _vp, _i32, _i64, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double

@@ -101,6 +101,8 @@ rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out) {
   inf.n_center_moves = s->n_moves;
   inf.nominal_svd_flops = s->nominal_svd_flops;
   inf.nominal_qr_flops = s->nominal_qr_flops;
+  inf.n_precond = s->n_precond;
+  inf.n_precond_fallback = s->n_precond_fallback;
   *out = inf;
   RCS_API_END
 }

@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "build.h"
+#include "chol.h"
 #include "circuit.h"
 #include "gemm_f64.h"
 #include "jacobi.h"
@@ -592,6 +593,8 @@ __global__ void k_to_device_layout(const double2* in, int da, int db, double2* o
 // ------------------------------------------------------------ workspace
 struct BuildWork {
   DevBuf T, X, X0, Wn, P, H, jac, sigma, sorted, order, scal, rot, tmp;
+  DevBuf G, Rd, Y, order_x, cflag;   // preconditioned split
+  std::vector<double> host_sorted;
   double2* wn_final = nullptr;   // orthonormal kept columns after svd_split
   void* host_rank_dev() {
     tmp.ensure(64);
@@ -698,6 +701,107 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
                      ws.P.as<double2>());
   HIP_LAUNCH_OK();
   return out;
+}
+
+static bool svd_precondition_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("RCS_SVD_PRECOND");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
+// Preconditioned split of X (len x cnt, X0 its copy): the Jacobi runs on
+// Y = R^H with R the Cholesky factor of X^H X (chol.hip), so it yields the
+// right singular vectors V of X and its singular values.  On success
+// ws.wn_final holds V_k (cnt x k, ld *ldw, X's column order) and ws.P the
+// k x len factor (X V_k)^H / nrm; the orthonormal factor is on X's column
+// side.  Returns false, with the caller free to run the plain split on the
+// untouched X0, when the Cholesky breaks down (X numerically rank
+// deficient) or when the Gram's rounding (about 1e-13 of ||X||_F^2 in each
+// squared singular value) could move the truncation: the last kept squared
+// singular value must exceed 1e-10 of the weight, and the discarded weight
+// must clear the eps threshold by 1e-9 of the weight on the side the rank
+// rule decided.
+static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl, int cap, double eps, bool renorm,
+                           std::vector<double>* spectrum_out, SplitResult& out, int* ldw) {
+  hipStream_t s = st.stream;
+  const int n = pl.cnt, len = pl.len;
+  RCS_REQUIRE(n <= SORT_MAX, "matrix too wide for the rank kernel");
+  double2* X = ws.X.as<double2>();
+  double2* X0 = ws.X0.as<double2>();
+  hipLaunchKernelGGL(k_colnorm, dim3(n), dim3(256), 0, s, X0, pl.ldx, len, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), n,
+                     reinterpret_cast<double*>(ws.host_rank_dev()));
+  HIP_LAUNCH_OK();
+  // columns in descending-norm order (the pivoting of the QR preconditioner)
+  ws.order_x.ensure((size_t)n * sizeof(int));
+  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, n, 0.0,
+                     ws.sorted.as<double>(), ws.order_x.as<int>(), ws.scal.as<RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(len, 256), n), dim3(256), 0, s, X0, pl.ldx, len,
+                     ws.order_x.as<int>(), X);
+  HIP_LAUNCH_OK();
+  const int ldg = (int)round_up(n, 64);
+  JacobiPlan py = jacobi_plan(n, n);
+  ws.G.ensure((size_t)ldg * ldg * sizeof(double2));
+  ws.Rd.ensure((size_t)ldg * 64 * sizeof(double2));
+  ws.Y.ensure((size_t)py.ldx * py.cnt_pad * sizeof(double2));
+  ws.jac.ensure(jacobi_work_bytes(py));
+  ws.cflag.ensure(sizeof(int));
+  HIP_OK(hipMemsetAsync(ws.cflag.p, 0, sizeof(int), s));
+  chol_precondition(X, pl.ldx, len, n, ws.G.as<double2>(), ldg, ws.Rd.as<double2>(), ws.Y.as<double2>(), py.ldx,
+                    py.cnt_pad, ws.cflag.as<int>(), s);
+  HIP_OK(hipMemcpyAsync(&ws.host_rank->w, ws.host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(ws.host_rot, ws.cflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const double fro2 = ws.host_rank->w;
+  if (*ws.host_rot != 0) return false;
+  double2* Y = ws.Y.as<double2>();
+  const int sweeps = jacobi_run(py, Y, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
+  st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
+  hipLaunchKernelGGL(k_colnorm, dim3(n), dim3(256), 0, s, Y, py.ldx, n, ws.sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, cap, eps,
+                     ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  ws.host_sorted.resize(n);
+  HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(ws.host_sorted.data(), ws.sorted.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const RankOut r = *ws.host_rank;
+  if (r.bad || r.k < 1) return false;
+  {
+    const double W = r.w;
+    double tk = 0.0;
+    for (int i = n - 1; i >= r.k; --i) tk += ws.host_sorted[i] * ws.host_sorted[i];
+    const double sk2 = ws.host_sorted[r.k - 1] * ws.host_sorted[r.k - 1];
+    const double thr = eps * W, delta = 1e-9 * W;
+    const bool decided = r.k == n || tk > thr + delta || (tk <= thr - delta && tk + sk2 > thr + delta);
+    if (!(sk2 >= 1e-10 * W) || !decided) return false;
+  }
+  out = SplitResult{r.k, r.nnz, sweeps, r.eps_step, r.w, r.nrm};
+  if (spectrum_out) spectrum_out->assign(ws.host_sorted.begin(), ws.host_sorted.end());
+  const int k = r.k;
+  // kept columns of Y J, normalised: V_k in the sorted basis; one
+  // Newton-Schulz step (into Y, free after the gather) makes them
+  // orthonormal to rounding
+  hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y, py.ldx,
+                     ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
+                     ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(k, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s,
+                     ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>(), Y);
+  HIP_LAUNCH_OK();
+  // P = (X_sorted V_k)^H / nrm, and V_k back in X's column order
+  project_rows(Y, py.ldx, X, pl.ldx, len, n, k, renorm ? 1.0 / r.nrm : 1.0, ws.P.as<double2>(), s);
+  unpermute_rows(Y, py.ldx, n, k, ws.order_x.as<int>(), ws.Wn.as<double2>(), s);
+  ws.wn_final = ws.Wn.as<double2>();
+  *ldw = py.ldx;
+  return true;
 }
 
 void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
@@ -959,13 +1063,19 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
       randomized_split(st, ws, ctx, i, gate16, cap_eff, eps, cycle, log_spectra))
     return;
   const bool randomized_tried = st.rsvd_log.size() > n_log;
+  // X = M (orient 1, rows (s1, a)) or M^H (orient 2, rows (s2, c)), with
+  // no more columns than rows.  The plain split puts the orthonormal factor
+  // on X's row side, the preconditioned one on its column side; a square M
+  // is oriented so that the preferred one leaves the centre where the next
+  // update needs it.
+  const bool precond = svd_precondition_enabled() && std::min(dl, dr) >= 64;
   int orient;
   if (dr < dl)
     orient = 1;
   else if (dl < dr)
     orient = 2;
   else
-    orient = prefer_left ? 2 : 1;
+    orient = (prefer_left != 0) == precond ? 1 : 2;
   const int len = orient == 1 ? 2 * dl : 2 * dr;
   const int cnt = orient == 1 ? 2 * dr : 2 * dl;
   JacobiPlan pl = jacobi_plan(len, cnt);
@@ -978,18 +1088,33 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
                      dr, orient, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
   HIP_LAUNCH_OK();
   std::vector<double> spec;
-  SplitResult r = svd_split(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr);
+  SplitResult r{};
+  int ldw = pl.ldx, p_row = pl.cnt, side = orient;
+  if (precond && svd_split_chol(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr, r, &ldw)) {
+    // orthonormal factor on X's column side: the other orientation's layout
+    side = 3 - orient;
+    p_row = len;
+    st.n_precond += 1;
+  } else {
+    if (precond) {
+      // X may hold the column-sorted copy: restore it from X0
+      HIP_OK(hipMemcpyAsync(ws.X.p, ws.X0.p, (size_t)pl.ldx * pl.cnt * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      st.n_precond_fallback += 1;
+    }
+    r = svd_split(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr);
+    ldw = pl.ldx;
+  }
   const int k = r.k;
   st.nominal_svd_flops += nominal_svd_flops(len, cnt);
   record_bond_spectrum(st, ws, ctx, i, k);
   if (ctx.o) ctx.prev_eps[i] = r.eps_step;
   hipLaunchKernelGGL(k_write_split, dim3(grid1d((int64_t)2 * k * (dl + dr))), dim3(256), 0, s,
-                     ws.wn_final, pl.ldx, ws.P.as<double2>(), pl.cnt, k, dl, dr, orient,
+                     ws.wn_final, ldw, ws.P.as<double2>(), p_row, k, dl, dr, side,
                      st.site[i], st.site[i + 1]);
   HIP_LAUNCH_OK();
   st.updates.push_back(UpdateRecord{i, cycle, dl, dm, dr, k, randomized_tried ? 2 : 0});
   st.dims[i + 1] = k;
-  st.center = orient == 1 ? i + 1 : i;
+  st.center = side == 1 ? i + 1 : i;
   st.log_fest += std::log1p(-r.eps_step);
   st.sum_eps += r.eps_step;
   st.n_trunc += 1;

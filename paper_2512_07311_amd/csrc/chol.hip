@@ -1,0 +1,283 @@
+// Triangular preconditioner for the one-sided Jacobi SVD: the Gram matrix
+// G = X^H X of the two-site matrix, its Cholesky factor G = R^H R (R upper
+// triangular), and Y = R^H in the Jacobi layout.
+//
+// X = Q R for some orthonormal Q, so X and R share singular values and right
+// singular vectors.  One-sided Jacobi on Y = R^H converges in far fewer
+// sweeps than on X (Drmac & Veselic, "New fast and accurate Jacobi SVD
+// algorithm", SIAM J. Matrix Anal. Appl. 29, 2008: the triangular factor is
+// one QR-iteration step closer to diagonal), and it leaves Y J = U_Y S with
+// U_Y the right singular vectors of X, so neither Q nor the accumulated
+// rotations J are needed.  R comes from the Gram rather than a Householder
+// QR, which costs relative accuracy below the Gram's rounding level
+// (singular values under ~1e-6 of the largest); the caller accepts the
+// result only where that level cannot change the truncation, and otherwise
+// runs the Jacobi on X itself.
+//
+// The factorisation is blocked by 64 columns, right-looking:
+//   panel kernel:  every workgroup factors the 64 x 64 diagonal block of G
+//                  in LDS (redundantly); workgroup 0 stores R_jj in a
+//                  separate array (the others are still reading G_jj), the
+//                  others invert R_jj in place and solve their 64-column tile
+//                  of the block row, R_jt = R_jj^{-H} G_jt;
+//   update kernel: G_tu -= R_jt^H R_ju for the upper tiles of the trailing
+//                  matrix, on the matrix cores.
+// G is stored column-major with ld = round_up(n, 64); the padding carries an
+// identity diagonal so that the padded matrix factors as blockdiag(R, I).
+#include "chol.h"
+#include "gemm_f64.h"
+
+namespace rcs {
+
+constexpr int CB = 64;          // Cholesky block
+constexpr int CHOL_THREADS = 256;
+
+// G (ld ldg, column-major) = X^H X over the upper tiles (blockIdx.y <=
+// blockIdx.x); entries outside n x n are the identity's.
+__global__ __launch_bounds__(GT_THREADS) void k_gram_upper(const double2* X, int ldx, int len, int n,
+                                                          double2* G, int ldg) {
+  if (blockIdx.y > blockIdx.x) return;
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int kk) -> double2 {
+    const double2 v = X[(int64_t)m * ldx + kk];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int kk, int c) -> double2 { return X[(int64_t)c * ldx + kk]; };
+  LoadA<decltype(fa), true> la{fa, m0, n, len};
+  LoadB<decltype(fb), false> lb{fb, n0, len, n};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, len, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r, col = n0 + c;
+    double2 v = make_double2(re, im);
+    if (m >= n || col >= n) v = make_double2(m == col ? 1.0 : 0.0, 0.0);
+    G[(int64_t)col * ldg + m] = v;
+  });
+}
+
+__device__ inline double2 cmul_c(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ inline double2 cmul_hc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// In-LDS Cholesky of the Hermitian 64 x 64 block T (upper part used):
+// T <- R with T = R^H R.  A pivot that is not positive and finite sets
+// *flag and is replaced by 1 (the result is then discarded by the caller).
+__device__ void chol64_lds(double2 (*T)[CB + 1], int* flag) {
+  __shared__ double inv_piv;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < CB; ++k) {
+    if (tid == 0) {
+      double d = T[k][k].x;
+      if (!(d > 0.0) || !(d < 1e300)) {
+        atomicExch(flag, 1);
+        d = 1.0;
+      }
+      const double r = sqrt(d);
+      T[k][k] = make_double2(r, 0.0);
+      inv_piv = 1.0 / r;
+    }
+    __syncthreads();
+    for (int c = k + 1 + tid; c < CB; c += CHOL_THREADS) {
+      const double2 v = T[k][c];
+      T[k][c] = make_double2(v.x * inv_piv, v.y * inv_piv);
+    }
+    __syncthreads();
+    const int m = CB - 1 - k;                    // trailing size
+    for (int e = tid; e < m * m; e += CHOL_THREADS) {
+      const int r = k + 1 + e / m, c = k + 1 + e % m;
+      if (r <= c) {
+        const double2 p = cmul_hc(T[k][r], T[k][c]);
+        T[r][c] = make_double2(T[r][c].x - p.x, T[r][c].y - p.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// In-place inverse of the upper-triangular T (64 x 64): columns left to
+// right, T[0:j, j] <- -T[0:j,0:j]^{-1}-part times the old column / T[j][j],
+// using the already inverted leading block.
+__device__ void trinv64_lds(double2 (*T)[CB + 1]) {
+  __shared__ double2 col[CB];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < CB; ++j) {
+    // inverse diagonal entry (real positive)
+    const double djj = 1.0 / T[j][j].x;
+    // new column entries i < j: -djj * sum_{m=i}^{j-1} Tinv[i][m] T[m][j]
+    if (tid < j) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int m = tid; m < j; ++m) {
+        const double2 p = cmul_c(T[tid][m], T[m][j]);
+        s.x += p.x;
+        s.y += p.y;
+      }
+      col[tid] = make_double2(-djj * s.x, -djj * s.y);
+    }
+    __syncthreads();
+    if (tid < j) T[tid][j] = col[tid];
+    if (tid == 0) T[j][j] = make_double2(djj, 0.0);
+    __syncthreads();
+  }
+}
+
+// Panel jb: diagonal factor (all workgroups), R_jj store (workgroup 0),
+// block-row solve R_jt = R_jj^{-H} G_jt (workgroup t, tile jb + t).
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd) {
+  __shared__ double2 T[CB][CB + 1];
+  __shared__ double2 A[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int j0 = jb * CB;
+  for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
+    const int r = e % CB, c = e / CB;
+    T[r][c] = G[(int64_t)(j0 + c) * ldg + j0 + r];
+  }
+  __syncthreads();
+  chol64_lds(T, flag);
+  if (blockIdx.x == 0) {
+    double2* rd = Rd + (int64_t)jb * CB * CB;
+    for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
+      const int r = e % CB, c = e / CB;
+      rd[e] = r <= c ? T[r][c] : make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const int t0 = j0 + blockIdx.x * CB;           // first column of this tile
+  for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
+    const int r = e % CB, c = e / CB;
+    A[r][c] = G[(int64_t)(t0 + c) * ldg + j0 + r];
+  }
+  trinv64_lds(T);                                 // T <- R_jj^{-1} (upper)
+  // out[r][c] = sum_{m <= r} conj(Rinv[m][r]) A[m][c]
+  const int c = tid & (CB - 1);
+  for (int r = tid >> 6; r < CB; r += CHOL_THREADS / CB) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int m = 0; m <= r; ++m) {
+      const double2 p = cmul_hc(T[m][r], A[m][c]);
+      s.x += p.x;
+      s.y += p.y;
+    }
+    G[(int64_t)(t0 + c) * ldg + j0 + r] = s;
+  }
+}
+
+// Trailing update after panel jb: tile (ti, tj), jb < ti <= tj < nb:
+// G_{ti,tj} -= R_{jb,ti}^H R_{jb,tj}.  blockIdx.x enumerates the pairs.
+__global__ __launch_bounds__(GT_THREADS) void k_chol_update(double2* G, int ldg, int nb, int jb) {
+  __shared__ SmemC64 sm;
+  const int T = nb - jb - 1;
+  // pair index -> (ti, tj) with ti <= tj, row-major over the upper triangle
+  int p = blockIdx.x, ti = 0;
+  while (p >= T - ti) {
+    p -= T - ti;
+    ++ti;
+  }
+  const int tj = ti + p;
+  const int r0 = (jb + 1 + ti) * CB, c0 = (jb + 1 + tj) * CB, k0 = jb * CB;
+  auto fa = [&](int m, int kk) -> double2 {
+    const double2 v = G[(int64_t)(r0 + m) * ldg + k0 + kk];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int kk, int n) -> double2 { return G[(int64_t)(c0 + n) * ldg + k0 + kk]; };
+  LoadA<decltype(fa), true> la{fa, 0, CB, CB};
+  LoadB<decltype(fb), false> lb{fb, 0, CB, CB};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, CB, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    double2* g = G + (int64_t)(c0 + c) * ldg + r0 + r;
+    *g = make_double2(g->x - re, g->y - im);
+  });
+}
+
+// Y (ldy x ncols, column-major) = R^H in the leading n x n block, zero
+// elsewhere; R's diagonal blocks are in Rd (64 x 64 each, column-major), its
+// off-diagonal blocks in the upper triangle of G.
+__global__ void k_chol_to_y(const double2* G, int ldg, const double2* Rd, int n, double2* Y, int ldy, int ncols) {
+  const int64_t tot = (int64_t)ldy * ncols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % ldy), j = (int)(e / ldy);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n && i >= j) {
+      // R[j][i], row j, column i
+      const double2 r = (i / CB == j / CB) ? Rd[(int64_t)(j / CB) * CB * CB + (i % CB) * CB + (j % CB)]
+                                           : G[(int64_t)i * ldg + j];
+      v = make_double2(r.x, -r.y);
+    }
+    Y[e] = v;
+  }
+}
+
+void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Y,
+                       int ldy, int ycols, int* flag_dev, hipStream_t s) {
+  RCS_REQUIRE(ldg % CB == 0 && ldg >= n, "Gram leading dimension must be a multiple of 64");
+  const int nb = ldg / CB;
+  hipLaunchKernelGGL(k_gram_upper, dim3(nb, nb), dim3(GT_THREADS), 0, s, X, ldx, len, n, G, ldg);
+  HIP_LAUNCH_OK();
+  for (int jb = 0; jb < nb; ++jb) {
+    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(CHOL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd);
+    HIP_LAUNCH_OK();
+    const int T = nb - jb - 1;
+    if (T > 0) {
+      hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(GT_THREADS), 0, s, G, ldg, nb, jb);
+      HIP_LAUNCH_OK();
+    }
+  }
+  const int64_t tot = (int64_t)ldy * ycols;
+  hipLaunchKernelGGL(k_chol_to_y, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65535)), dim3(256), 0, s, G,
+                     ldg, Rd, n, Y, ldy, ycols);
+  HIP_LAUNCH_OK();
+}
+
+// P (k x len, row-major) = scale * (X U)^H with X len x n (ld ldx) and U
+// n x k (ld ldu): P[j][r] = scale * sum_i conj(U[i][j]) conj(X[r][i]).
+__global__ __launch_bounds__(GT_THREADS) void k_project_rows(const double2* U, int ldu, const double2* X, int ldx,
+                                                            int len, int n, int k, double scale, double2* P) {
+  __shared__ SmemC64 sm;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int j, int i) -> double2 {
+    const double2 v = U[(int64_t)j * ldu + i];
+    return make_double2(v.x, -v.y);
+  };
+  auto fb = [&](int i, int r) -> double2 {
+    const double2 v = X[(int64_t)i * ldx + r];
+    return make_double2(v.x, -v.y);
+  };
+  LoadA<decltype(fa), true> la{fa, m0, k, n};
+  LoadB<decltype(fb), true> lb{fb, n0, n, len};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, n, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int j = m0 + r, col = n0 + c;
+    if (j < k && col < len) P[(int64_t)j * len + col] = make_double2(re * scale, im * scale);
+  });
+}
+
+void project_rows(const double2* U, int ldu, const double2* X, int ldx, int len, int n, int k, double scale,
+                  double2* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_project_rows, dim3(ceil_div(len, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s, U, ldu,
+                     X, ldx, len, n, k, scale, P);
+  HIP_LAUNCH_OK();
+}
+
+// out[j*ld + order[i]] = in[j*ld + i] for i < n, j < k: rows back to the
+// caller's column order.
+__global__ void k_unpermute_rows(const double2* in, int ld, int n, int k, const int* order, double2* out) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[(int64_t)j * ld + order[i]] = in[(int64_t)j * ld + i];
+}
+
+void unpermute_rows(const double2* in, int ld, int n, int k, const int* order, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpermute_rows, dim3(ceil_div(n, 256), k), dim3(256), 0, s, in, ld, n, k, order, out);
+  HIP_LAUNCH_OK();
+}
+
+}  // namespace rcs

@@ -81,6 +81,7 @@ struct rcs_state_s {
   double log_fest = 0.0, sum_eps = 0.0;
   double build_seconds = 0.0, svd_seconds = 0.0;
   int n_moves = 0;
+  int n_precond = 0, n_precond_fallback = 0;   // preconditioned splits, and those redone plainly
   double nominal_svd_flops = 0.0, nominal_qr_flops = 0.0;
   std::vector<rcs::SpectrumRecord> spectra;
   std::vector<rcs::UpdateRecord> updates;
