@@ -225,10 +225,13 @@ typedef struct {
   int32_t n_center_moves;  /* single-site orthogonalisations (centre moves) */
   double nominal_svd_flops;/* sum over full SVDs of 4 (14 m n^2 + 8 n^3),    */
                            /* m >= n the two-site matrix shape              */
-  double nominal_qr_flops; /* sum over centre moves of 4 (2 m n^2 - 2n^3/3) */
+  double nominal_qr_flops; /* sum over the centre moves done by the Jacobi */
+                           /* orthogonalisation of 4 (2 m n^2 - 2n^3/3)     */
   int32_t n_precond;       /* full SVDs done on the Cholesky-preconditioned */
                            /* matrix (Jacobi on R^H, R^H R = X^H X)         */
   int32_t n_precond_fallback; /* preconditioned attempts redone on X itself */
+  int32_t n_center_moves_cholqr; /* centre moves done by CholeskyQR (the   */
+                           /* others by the Jacobi orthogonalisation)       */
 } rcs_state_info;
 
 rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out);
@@ -297,6 +300,19 @@ rcs_status rcs_state_rsvd_log(rcs_state s, int32_t* n_records, int64_t* n_values
  * x_dev is overwritten.  Errors: NUMERIC if not converged. */
 rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev, double* u_dev,
                           void* stream);
+
+/* Thin QR of a complex len x cnt matrix (cnt <= len, 64 <= cnt <= 4096),
+ * column-major in x_dev, as the build's centre moves compute it
+ * (CholeskyQR: R from the Cholesky factor of X^H X, Q = X R^{-1}, then three
+ * Newton-Schulz steps Q <- Q (3I - Q^H Q)/2): q_dev (len x cnt,
+ * column-major) has orthonormal columns spanning range(X), r_dev (cnt x cnt,
+ * column-major) = Q^H X, upper triangular up to the Newton-Schulz
+ * correction (about u cond(X)^2 relative), and X = Q R.  x_dev is not
+ * modified.  Errors: NUMERIC when X is numerically rank deficient or its
+ * condition number exceeds about 1e6 (the Cholesky breaks down or
+ * |I - Q^H Q| exceeds 1e-4 after the first pass); the build then uses the
+ * Jacobi orthogonalisation instead. */
+rcs_status rcs_cholqr(int32_t len, int32_t cnt, const double* x_dev, double* q_dev, double* r_dev, void* stream);
 
 /* Two-site contraction: theta'[(s1,a),(s2,c)] = sum_{s1',s2'} G[(s1,s2),(s1',s2')]
  * sum_b A[a,s1',b] B[b,s2',c] with A (dl,2,dm), B (dm,2,dr) in export

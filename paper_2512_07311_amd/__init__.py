@@ -65,7 +65,7 @@ class StateInfo(C.Structure):
                 ("svd_seconds", C.c_double), ("device_bytes", C.c_int64),
                 ("n_center_moves", C.c_int32), ("nominal_svd_flops", C.c_double),
                 ("nominal_qr_flops", C.c_double), ("n_precond", C.c_int32),
-                ("n_precond_fallback", C.c_int32)]
+                ("n_precond_fallback", C.c_int32), ("n_center_moves_cholqr", C.c_int32)]
 
 
 _vp, _i32, _i64, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -95,6 +95,7 @@ _SIGS = {
     "rcs_state_updates": [_vp, _P(_i32), _P(_i32)],
     "rcs_state_rsvd_log": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d), _P(C.c_float), _P(_d)],
     "rcs_svd_jacobi": [_i32, _i32, _vp, _vp, _vp, _vp],
+    "rcs_cholqr": [_i32, _i32, _vp, _vp, _vp, _vp],
     "rcs_two_site": [_i32, _i32, _i32, _vp, _vp, _P(_d), _i32, _vp, _vp],
     "rcs_rsvd": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _P(_d), _vp],
     "rcs_rsvd_basis": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _vp],
@@ -392,6 +393,14 @@ def svd_jacobi(x, s, u, stream=None):
     len x cnt matrix); overwritten.  s: float64 (cnt,), u: complex128 like x."""
     cnt, ln = x.shape
     _check(_lib.rcs_svd_jacobi(ln, cnt, _ptr(x), _ptr(s), _ptr(u), _stream_ptr(stream)))
+
+
+def cholqr(x, q, r, stream=None):
+    """x: complex128 device tensor (cnt, len) holding the columns of a
+    column-major len x cnt matrix (not modified); q: like x; r: complex128
+    (cnt, cnt) receiving the columns of R (X = Q R, Q orthonormal)."""
+    cnt, ln = x.shape
+    _check(_lib.rcs_cholqr(ln, cnt, _ptr(x), _ptr(q), _ptr(r), _stream_ptr(stream)))
 
 
 def two_site(a, b, gate, out, precision="c128", stream=None):

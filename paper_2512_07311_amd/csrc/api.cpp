@@ -103,6 +103,7 @@ rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out) {
   inf.nominal_qr_flops = s->nominal_qr_flops;
   inf.n_precond = s->n_precond;
   inf.n_precond_fallback = s->n_precond_fallback;
+  inf.n_center_moves_cholqr = s->n_moves_cholqr;
   *out = inf;
   RCS_API_END
 }

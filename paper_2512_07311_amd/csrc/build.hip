@@ -568,6 +568,21 @@ __global__ void k_copy_out(const double2* X, int ldx, int len, int cnt, const in
   }
 }
 
+// q[j * len + r] = Q[r][j] (Q: ld ldq) and r[c * cnt + j] = P[j][c] (P row-major
+// cnt x cnt): the thin QR factors in column-major layout.
+__global__ void k_export_qr(const double2* Q, int ldq, const double2* P, int len, int cnt, double2* q, double2* r) {
+  const int64_t tot = (int64_t)len * cnt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % len), j = (int)(e / len);
+    q[e] = Q[(int64_t)j * ldq + row];
+    if (e < (int64_t)cnt * cnt) {
+      const int jj = (int)(e % cnt), c = (int)(e / cnt);
+      r[e] = P[(int64_t)jj * cnt + c];
+    }
+  }
+}
+
 // q_dev[j * len + r] = Q[r][j]: the fp64 basis the range finder leaves.
 __global__ void k_copy_basis(const double2* Q, int ldq, int len, int l, double2* out) {
   const int64_t tot = (int64_t)len * l;
@@ -594,6 +609,7 @@ __global__ void k_to_device_layout(const double2* in, int da, int db, double2* o
 struct BuildWork {
   DevBuf T, X, X0, Wn, P, H, jac, sigma, sorted, order, scal, rot, tmp;
   DevBuf G, Rd, Y, order_x, cflag;   // preconditioned split
+  DevBuf Ri, Tq, qdev;                // CholeskyQR centre moves
   std::vector<double> host_sorted;
   double2* wn_final = nullptr;   // orthonormal kept columns after svd_split
   void* host_rank_dev() {
@@ -832,8 +848,64 @@ static double nominal_qr_flops(int a, int b) {
   return 4.0 * (2.0 * m * n * n - 2.0 * n * n * n / 3.0);
 }
 
-// Move the orthogonality centre one step (exact orthogonalisation by SVD,
-// dropping only exact zeros).
+static bool cholqr_moves_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("RCS_CHOLQR_MOVES");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
+// CholeskyQR of the loaded site matrix X (len x cnt): Q1 = X R^{-1} with R
+// the Cholesky factor of X^H X, then Newton-Schulz steps Q <- Q (3I -
+// Q^H Q) / 2.  Q1's orthogonality defect is about u cond(X)^2; the first
+// step measures it and the move is left to the Jacobi path (false) when it
+// exceeds 1e-4 (cond(X) above about 1e6) or the Cholesky breaks down
+// (X rank deficient).  From 1e-4 two more steps reach rounding level
+// (e -> 3e^2/4 each).  On success ws.wn_final holds Q (ld pl.ldx).
+static bool move_cholqr(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl) {
+  hipStream_t s = st.stream;
+  const int len = pl.len, n = pl.cnt;
+  const int ldg = (int)round_up(n, 64);
+  ws.G.ensure((size_t)ldg * ldg * sizeof(double2));
+  ws.Rd.ensure((size_t)ldg * 64 * sizeof(double2));
+  ws.Ri.ensure((size_t)ldg * ldg * sizeof(double2));
+  ws.Tq.ensure((size_t)ldg * ldg * sizeof(double2));
+  ws.cflag.ensure(sizeof(int));
+  ws.qdev.ensure(sizeof(double));
+  HIP_OK(hipMemsetAsync(ws.cflag.p, 0, sizeof(int), s));
+  double2* Wn = ws.Wn.as<double2>();
+  double2* X = ws.X.as<double2>();
+  cholqr(ws.X0.as<double2>(), pl.ldx, len, n, ws.G.as<double2>(), ldg, ws.Rd.as<double2>(), ws.Ri.as<double2>(),
+         ws.Tq.as<double2>(), Wn, pl.ldx, ws.cflag.as<int>(), s);
+  double2* src = Wn;
+  double2* dst = X;
+  for (int it = 0; it < 3; ++it) {
+    hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(n, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s, src, pl.ldx,
+                       len, n, ws.H.as<double2>());
+    HIP_LAUNCH_OK();
+    if (it == 0) {
+      max_dev_identity(ws.H.as<double2>(), n, ws.qdev.as<double>(), s);
+      double dev = 0.0;
+      HIP_OK(hipMemcpyAsync(ws.host_rot, ws.cflag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipMemcpyAsync(&ws.host_rank->w, ws.qdev.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      dev = ws.host_rank->w;      // max |H - I| = max |I - Q^H Q| / 2
+      if (*ws.host_rot != 0 || !(dev <= 0.5e-4)) return false;
+    }
+    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(n, GT_N), ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, src,
+                       pl.ldx, len, n, ws.H.as<double2>(), dst);
+    HIP_LAUNCH_OK();
+    std::swap(src, dst);
+  }
+  ws.wn_final = src;
+  return true;
+}
+
+// Move the orthogonality centre one step: X = Q P with Q orthonormal
+// (CholeskyQR, or, when X is rank deficient or too ill-conditioned for it,
+// the Jacobi orthogonalisation that drops exact zeros); Q stays, P is
+// absorbed into the neighbour.
 static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   hipStream_t s = st.stream;
   const int c = st.center;
@@ -847,10 +919,23 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   hipLaunchKernelGGL(k_load_site, dim3(grid1d((int64_t)2 * dl * dr)), dim3(256), 0, s, st.site[c], dl, dr,
                      right ? 1 : 0, ws.X.as<double2>(), ws.X0.as<double2>(), pl.ldx);
   HIP_LAUNCH_OK();
-  SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr, nullptr, true);
-  const int k = r.k;
+  int k;
+  if (cholqr_moves_enabled() && cnt >= 64 && cnt <= len && move_cholqr(st, ws, pl)) {
+    k = cnt;
+    st.n_moves_cholqr += 1;
+    hipLaunchKernelGGL(k_project, dim3(ceil_div(cnt, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
+                       ws.wn_final, ws.X0.as<double2>(), pl.ldx, len, k, cnt, 1.0, ws.P.as<double2>());
+    HIP_LAUNCH_OK();
+  } else {
+    // the CholeskyQR attempt (if any) left X untouched only where it ran
+    // out of steps: reload it
+    HIP_OK(hipMemcpyAsync(ws.X.p, ws.X0.p, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr, nullptr, true);
+    k = r.k;
+    // nominal work of the moves the Jacobi kernels do
+    st.nominal_qr_flops += nominal_qr_flops(len, cnt);
+  }
   st.n_moves += 1;
-  st.nominal_qr_flops += nominal_qr_flops(len, cnt);
   hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
                      ws.wn_final, pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
   HIP_LAUNCH_OK();
@@ -1372,6 +1457,35 @@ rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev
   HIP_LAUNCH_OK();
   hipLaunchKernelGGL(rcs::k_copy_out, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s, X, pl.ldx, len, cnt,
                      ws->order.as<int>(), ws->sorted.as<double>(), s_dev, reinterpret_cast<double2*>(u_dev));
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  RCS_API_END
+}
+
+rcs_status rcs_cholqr(int32_t len, int32_t cnt, const double* x_dev, double* q_dev, double* r_dev, void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(x_dev && q_dev && r_dev, "null device pointer");
+  RCS_REQUIRE(cnt >= 64 && cnt <= len && cnt <= rcs::SORT_MAX && len <= 16384, "bad matrix shape");
+  hipStream_t s = rcs::as_stream(stream);
+  rcs::JacobiPlan pl = rcs::jacobi_plan(len, cnt);
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  rcs::ensure_work(*ws, pl, 0);
+  HIP_OK(hipMemsetAsync(ws->X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws->X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  hipLaunchKernelGGL(rcs::k_copy_in, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x_dev), len, cnt, ws->X0.as<double2>(), pl.ldx);
+  HIP_LAUNCH_OK();
+  rcs_state_s tmp;
+  tmp.stream = s;
+  if (!rcs::move_cholqr(tmp, *ws, pl))
+    rcs::fail(RCS_ERR_NUMERIC, "CholeskyQR: matrix rank deficient or too ill-conditioned");
+  // Q out (len x cnt), R = Q^H X (cnt x cnt) as a row-major P then transposed out
+  hipLaunchKernelGGL(rcs::k_project, dim3(rcs::ceil_div(cnt, rcs::GT_N), rcs::ceil_div(cnt, rcs::GT_M)),
+                     dim3(rcs::GT_THREADS), 0, s, ws->wn_final, ws->X0.as<double2>(), pl.ldx, len, cnt, cnt, 1.0,
+                     ws->P.as<double2>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_export_qr, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s, ws->wn_final, pl.ldx,
+                     ws->P.as<double2>(), len, cnt, reinterpret_cast<double2*>(q_dev), reinterpret_cast<double2*>(r_dev));
   HIP_LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
   RCS_API_END

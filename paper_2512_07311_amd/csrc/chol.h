@@ -14,6 +14,15 @@ namespace rcs {
 // not positive, i.e. X is numerically rank deficient.
 void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Y,
                        int ldy, int ycols, int* flag_dev, hipStream_t s);
+// CholeskyQR: R from the Cholesky factor of X^H X (X: len x n, ld ldx),
+// R^{-1} in Ri (ldg x ldg, upper, by recursive doubling of its 64 x 64
+// diagonal blocks; T is ldg x ldg scratch), Q = X R^{-1} (ld ldq).  Q is
+// orthonormal up to about u cond(X)^2; *flag_dev is set on a non-positive
+// pivot.
+void cholqr(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Ri, double2* T,
+            double2* Q, int ldq, int* flag_dev, hipStream_t s);
+// *dev = max entry of |H - I|, H k x k row-major (one workgroup).
+void max_dev_identity(const double2* H, int k, double* dev, hipStream_t s);
 // P (k x len, row-major) = scale (X U)^H; X len x n (ld ldx), U n x k (ld ldu).
 void project_rows(const double2* U, int ldu, const double2* X, int ldx, int len, int n, int k, double scale,
                   double2* P, hipStream_t s);

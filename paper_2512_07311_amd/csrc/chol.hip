@@ -128,7 +128,8 @@ __device__ void trinv64_lds(double2 (*T)[CB + 1]) {
 
 // Panel jb: diagonal factor (all workgroups), R_jj store (workgroup 0),
 // block-row solve R_jt = R_jj^{-H} G_jt (workgroup t, tile jb + t).
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd) {
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd,
+                                                             double2* Ri) {
   __shared__ double2 T[CB][CB + 1];
   __shared__ double2 A[CB][CB + 1];
   const int tid = threadIdx.x;
@@ -144,6 +145,15 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_panel(double2* G, int ldg
     for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
       const int r = e % CB, c = e / CB;
       rd[e] = r <= c ? T[r][c] : make_double2(0.0, 0.0);
+    }
+    if (Ri) {
+      // diagonal block of R^{-1} (ld ldg)
+      __syncthreads();
+      trinv64_lds(T);
+      for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
+        const int r = e % CB, c = e / CB;
+        Ri[(int64_t)(j0 + c) * ldg + j0 + r] = r <= c ? T[r][c] : make_double2(0.0, 0.0);
+      }
     }
     return;
   }
@@ -214,14 +224,16 @@ __global__ void k_chol_to_y(const double2* G, int ldg, const double2* Rd, int n,
   }
 }
 
-void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Y,
-                       int ldy, int ycols, int* flag_dev, hipStream_t s) {
+// Gram and blocked Cholesky (R's off-diagonal blocks in G, diagonal blocks
+// in Rd, diagonal blocks of R^{-1} in Ri when Ri is not null).
+static void gram_cholesky(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Ri,
+                          int* flag_dev, hipStream_t s) {
   RCS_REQUIRE(ldg % CB == 0 && ldg >= n, "Gram leading dimension must be a multiple of 64");
   const int nb = ldg / CB;
   hipLaunchKernelGGL(k_gram_upper, dim3(nb, nb), dim3(GT_THREADS), 0, s, X, ldx, len, n, G, ldg);
   HIP_LAUNCH_OK();
   for (int jb = 0; jb < nb; ++jb) {
-    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(CHOL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd);
+    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(CHOL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd, Ri);
     HIP_LAUNCH_OK();
     const int T = nb - jb - 1;
     if (T > 0) {
@@ -229,9 +241,104 @@ void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, in
       HIP_LAUNCH_OK();
     }
   }
+}
+
+void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Y,
+                       int ldy, int ycols, int* flag_dev, hipStream_t s) {
+  gram_cholesky(X, ldx, len, n, G, ldg, Rd, nullptr, flag_dev, s);
   const int64_t tot = (int64_t)ldy * ycols;
   hipLaunchKernelGGL(k_chol_to_y, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65535)), dim3(256), 0, s, G,
                      ldg, Rd, n, Y, ldy, ycols);
+  HIP_LAUNCH_OK();
+}
+
+// Batched column-major complex GEMM on sub-blocks: for batch z,
+// D_z = alpha A_z B_z with A_z = A + z sa (M x K, ld lda), B_z = B + z sb
+// (K x N, ld ldb), D_z = D + z sd (M x N, ld ldd), overwritten.
+__global__ __launch_bounds__(GT_THREADS) void k_cgemm_cm(const double2* A, int lda, int64_t sa, const double2* B,
+                                                        int ldb, int64_t sb, double2* D, int ldd, int64_t sd, int M,
+                                                        int N, int K, double alpha) {
+  __shared__ SmemC64 sm;
+  const int64_t z = blockIdx.z;
+  const double2* a = A + z * sa;
+  const double2* b = B + z * sb;
+  double2* d = D + z * sd;
+  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
+  auto fa = [&](int m, int k) -> double2 { return a[(int64_t)k * lda + m]; };
+  auto fb = [&](int k, int n) -> double2 { return b[(int64_t)n * ldb + k]; };
+  LoadA<decltype(fa), false> la{fa, m0, M, K};
+  LoadB<decltype(fb), false> lb{fb, n0, K, N};
+  AccC64 acc;
+  acc_zero(acc);
+  cgemm_mainloop(la, lb, K, sm, acc);
+  acc_foreach(acc, [&](int r, int c, double re, double im) {
+    const int m = m0 + r, n = n0 + c;
+    if (m < M && n < N) d[(int64_t)n * ldd + m] = make_double2(alpha * re, alpha * im);
+  });
+}
+
+static void cgemm_cm(const double2* A, int lda, int64_t sa, const double2* B, int ldb, int64_t sb, double2* D,
+                     int ldd, int64_t sd, int M, int N, int K, double alpha, int batch, hipStream_t s) {
+  if (batch <= 0 || M <= 0 || N <= 0) return;
+  hipLaunchKernelGGL(k_cgemm_cm, dim3(ceil_div(N, GT_N), ceil_div(M, GT_M), batch), dim3(GT_THREADS), 0, s, A, lda,
+                     sa, B, ldb, sb, D, ldd, sd, M, N, K, alpha);
+  HIP_LAUNCH_OK();
+}
+
+// R^{-1} (upper, ld ldg, lower part zero) from its 64 x 64 diagonal blocks
+// (already in Ri) by recursive doubling: for blocks [A | C] of the leading
+// diagonal, R^{-1}_{AC} = -R^{-1}_{AA} R_{AC} R^{-1}_{CC}, all pairs of a
+// level at once (two GEMM launches per level; T is an ldg x ldg scratch).
+static void triangular_inverse(const double2* G, int ldg, double2* Ri, double2* T, hipStream_t s) {
+  for (int h = CB; h < ldg; h *= 2) {
+    const int full = ldg / (2 * h);              // pairs with |C| = h
+    const int tail0 = full * 2 * h;              // a last pair with |C| < h
+    const int64_t stride = (int64_t)2 * h * ldg + 2 * h;
+    // T_AC = R_AC R^{-1}_CC, then Ri_AC = -R^{-1}_AA T_AC
+    cgemm_cm(G + (int64_t)h * ldg, ldg, stride, Ri + (int64_t)h * ldg + h, ldg, stride, T + (int64_t)h * ldg, ldg,
+             stride, h, h, h, 1.0, full, s);
+    cgemm_cm(Ri, ldg, stride, T + (int64_t)h * ldg, ldg, stride, Ri + (int64_t)h * ldg, ldg, stride, h, h, h, -1.0,
+             full, s);
+    const int hc = ldg - tail0 - h;
+    if (hc > 0) {
+      const int64_t a0 = (int64_t)tail0 * ldg + tail0, c0 = (int64_t)(tail0 + h) * ldg + (tail0 + h);
+      const int64_t ac = (int64_t)(tail0 + h) * ldg + tail0;
+      cgemm_cm(G + ac, ldg, 0, Ri + c0, ldg, 0, T + ac, ldg, 0, h, hc, hc, 1.0, 1, s);
+      cgemm_cm(Ri + a0, ldg, 0, T + ac, ldg, 0, Ri + ac, ldg, 0, h, hc, h, -1.0, 1, s);
+    }
+  }
+}
+
+void cholqr(const double2* X, int ldx, int len, int n, double2* G, int ldg, double2* Rd, double2* Ri, double2* T,
+            double2* Q, int ldq, int* flag_dev, hipStream_t s) {
+  HIP_OK(hipMemsetAsync(Ri, 0, (size_t)ldg * ldg * sizeof(double2), s));
+  gram_cholesky(X, ldx, len, n, G, ldg, Rd, Ri, flag_dev, s);
+  triangular_inverse(G, ldg, Ri, T, s);
+  cgemm_cm(X, ldx, 0, Ri, ldg, 0, Q, ldq, 0, len, n, n, 1.0, 1, s);
+}
+
+// *dev = max over entries of |H - I| (H k x k, row-major), one workgroup.
+__global__ void k_max_dev_identity(const double2* H, int k, double* dev) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += 256) {
+    const int r = (int)(e / k), c = (int)(e % k);
+    const double2 h = H[e];
+    const double re = h.x - (r == c ? 1.0 : 0.0);
+    m = fmax(m, fmax(fabs(re), fabs(h.y)));
+    if (!(h.x == h.x) || !(h.y == h.y)) m = 1e300;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h2 = 128; h2 > 0; h2 >>= 1) {
+    if ((int)threadIdx.x < h2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dev = red[0];
+}
+
+void max_dev_identity(const double2* H, int k, double* dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_dev_identity, dim3(1), dim3(256), 0, s, H, k, dev);
   HIP_LAUNCH_OK();
 }
 

@@ -82,6 +82,7 @@ struct rcs_state_s {
   double build_seconds = 0.0, svd_seconds = 0.0;
   int n_moves = 0;
   int n_precond = 0, n_precond_fallback = 0;   // preconditioned splits, and those redone plainly
+  int n_moves_cholqr = 0;                        // centre moves done by CholeskyQR
   double nominal_svd_flops = 0.0, nominal_qr_flops = 0.0;
   std::vector<rcs::SpectrumRecord> spectra;
   std::vector<rcs::UpdateRecord> updates;

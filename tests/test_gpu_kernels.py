@@ -1,6 +1,7 @@
 """GPU parity of the stage-level kernels through the C-ABI: the fp64
 one-sided Jacobi SVD against the defining properties of an SVD and LAPACK,
-and the two-site contraction against the oracle's definition."""
+the centre moves' QR against LAPACK's, and the two-site contraction against
+the oracle's definition."""
 import numpy as np
 import pytest
 
@@ -105,3 +106,53 @@ def test_two_site_reduced_precision(env, precision):
         exact = np.einsum("xyst,stac->axyc", G4, np.einsum("asb,btc->stac", A, B)).transpose(1, 0, 2, 3).reshape(2 * dl, 2 * dr)
         rel = np.linalg.norm(got - exact) / np.linalg.norm(exact)
         assert rel < (2.0 ** -20 if precision == "c64" else 2.0 ** -14)
+
+
+# ------------------------------------------------------------------ QR
+def _qr_gpu(rcs, torch, M):
+    ln, cnt = M.shape
+    x = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
+    q = torch.zeros(cnt, ln, dtype=torch.complex128, device="cuda")
+    r = torch.zeros(cnt, cnt, dtype=torch.complex128, device="cuda")
+    rcs.cholqr(x, q, r)
+    return q.cpu().numpy().T, r.cpu().numpy().T
+
+
+QR_SHAPES = [(2048, 1024, 1e3), (300, 130, 1e2), (1100, 1100, 1e4), (2048, 2048, 1e5), (512, 64, 10.0)]
+
+
+@pytest.mark.parametrize("ln,cnt,cond", QR_SHAPES)
+def test_cholqr_against_numpy_qr(env, ln, cnt, cond):
+    """The centre moves' QR (CholeskyQR + Newton-Schulz) against LAPACK's
+    Householder QR: orthonormal Q and X = Q R to rounding (all a centre move
+    needs: the state is unchanged for any orthonormal Q with X = Q R), R
+    upper triangular up to the Newton-Schulz correction, and the same
+    factorisation as numpy's up to the phase of each column (Q_np^H Q
+    diagonal and unimodular, |diag R| equal) within CholeskyQR's forward
+    error, which grows like u cond(X)^2 (the Gram squares the conditioning;
+    Householder's grows like u cond(X))."""
+    rcs, torch = env
+    M = inputs.planted_matrix(ln, cnt, np.geomspace(1.0, 1.0 / cond, cnt), seed=ln + cnt)
+    Q, R = _qr_gpu(rcs, torch, M)
+    nrm = np.linalg.norm(M)
+    assert np.abs(Q.conj().T @ Q - np.eye(cnt)).max() < 1e-13
+    assert np.linalg.norm(M - Q @ R) <= 1e-14 * nrm * np.sqrt(cnt)
+    assert np.abs(np.tril(R, -1)).max() <= 1e-10 * np.abs(R).max()
+    Qn, Rn = np.linalg.qr(M)
+    D = Qn.conj().T @ Q
+    fwd = max(1e-10, 1e-15 * cond ** 2)
+    assert np.abs(D - np.diag(np.diag(D))).max() < fwd
+    assert np.abs(np.abs(np.diag(D)) - 1.0).max() < fwd
+    assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(Rn)), rtol=fwd, atol=1e-14 * nrm)
+
+
+@pytest.mark.parametrize("kind", ["rank_deficient", "ill_conditioned"])
+def test_cholqr_refuses_what_it_cannot_orthogonalise(env, kind):
+    """Rank-deficient and badly conditioned inputs are reported (NUMERIC), not
+    returned with a non-orthonormal Q; the build then takes the Jacobi path."""
+    rcs, torch = env
+    spec = np.r_[np.ones(200), np.zeros(56)] if kind == "rank_deficient" else np.geomspace(1.0, 1e-9, 256)
+    M = inputs.planted_matrix(600, 256, spec, seed=9)
+    with pytest.raises(rcs.RcsError) as ei:
+        _qr_gpu(rcs, torch, M)
+    assert ei.value.status == 5
