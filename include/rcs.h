@@ -254,6 +254,23 @@ rcs_status rcs_state_export(rcs_state s, double* tensors_host, int64_t count_dou
 rcs_status rcs_state_import(int32_t n, const int32_t* dims_host, const int32_t* snake_host,
                             const double* tensors_host, int32_t canonical, void* stream,
                             rcs_state* out);
+
+/* Section 3.2, stage 2: the built state is persisted once and loaded by
+ * every independent sampling job.  rcs_state_save writes the state's
+ * layout, estimated fidelity and site tensors to `path` (written to
+ * path + ".tmp" and renamed, so a reader never sees a partial file);
+ * rcs_state_load creates a state from such a file on the calling thread's
+ * current device, with its work on `stream` (NULL = null stream).  File
+ * layout, little-endian: magic "RCSMPS1\n"; int32 version (1), n,
+ * canonical, 0; float64 log F_est; int32 dims[n+1]; int32 snake[n]; the
+ * site tensors in the rcs_state_export layout; uint64 FNV-1a checksum of
+ * everything before it (64-bit words, then trailing bytes).  Loading a
+ * canonical state and sampling a shot range gives the same bits as the
+ * saving process would (shots depend only on state, seed and shot index).
+ * Errors: INVALID_ARG for unreadable, truncated or corrupt files (bad
+ * magic, version, sizes or checksum), DEVICE when writing fails. */
+rcs_status rcs_state_save(rcs_state s, const char* path);
+rcs_status rcs_state_load(const char* path, void* stream, rcs_state* out);
 void rcs_state_destroy(rcs_state s);
 
 /* Per-update record of a build with log_spectra = 1: count, then for record

@@ -91,6 +91,8 @@ _SIGS = {
     "rcs_state_set_stream": [_vp, _vp],
     "rcs_state_export": [_vp, _P(_d), _i64, _P(_i64)],
     "rcs_state_import": [_i32, _P(_i32), _P(_i32), _P(_d), _i32, _vp, _P(_vp)],
+    "rcs_state_save": [_vp, C.c_char_p],
+    "rcs_state_load": [C.c_char_p, _vp, _P(_vp)],
     "rcs_state_spectra": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d)],
     "rcs_state_updates": [_vp, _P(_i32), _P(_i32)],
     "rcs_state_rsvd_log": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d), _P(C.c_float), _P(_d)],
@@ -256,6 +258,17 @@ class State:
                                      flat.ctypes.data_as(_P(_d)), 1 if canonical else 0,
                                      _stream_ptr(stream), C.byref(h)))
         return State(h)
+
+    @staticmethod
+    def load(path, stream=None):
+        """A state saved by State.save (rcs_state_load)."""
+        h = C.c_void_p()
+        _check(_lib.rcs_state_load(os.fsencode(path), _stream_ptr(stream), C.byref(h)))
+        return State(h)
+
+    def save(self, path):
+        """Persist the state (rcs_state_save)."""
+        _check(_lib.rcs_state_save(self.h, os.fsencode(path)))
 
     def info(self):
         inf = StateInfo()

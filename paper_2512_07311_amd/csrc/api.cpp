@@ -1,4 +1,8 @@
 // C ABI entry points: circuits, state access, sampling, amplitudes, XEB.
+#include <memory>
+#include <string>
+#include <cstring>
+#include <cstdio>
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -202,6 +206,115 @@ rcs_status rcs_state_import(int32_t n, const int32_t* dims_host, const int32_t* 
   st->canonical = canonical != 0;
   st->center = 0;
   *out = st.release();
+  RCS_API_END
+}
+
+// ------------------------------------------------------------ persistence
+// File layout (little-endian): 8-byte magic "RCSMPS1\n"; int32 version (1),
+// n, canonical, reserved (0); float64 log_fidelity_est; int32 dims[n+1];
+// int32 snake[n]; the site tensors as rcs_state_export writes them (A_k of
+// shape (dims[k], 2, dims[k+1]), row-major complex128); uint64 checksum =
+// FNV-1a over the preceding bytes taken as 64-bit words.
+namespace {
+constexpr char kMagic[8] = {'R', 'C', 'S', 'M', 'P', 'S', '1', '\n'};
+
+struct Fnv64 {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, c + i, 8);
+      h = (h ^ w) * 1099511628211ull;
+    }
+    for (; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+};
+
+struct FileCloser {
+  void operator()(std::FILE* f) const {
+    if (f) std::fclose(f);
+  }
+};
+using FilePtr = std::unique_ptr<std::FILE, FileCloser>;
+}  // namespace
+
+rcs_status rcs_state_save(rcs_state s, const char* path) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(s && path, "null argument");
+  int64_t need = 0;
+  rcs_status e = rcs_state_export(s, nullptr, 0, &need);
+  if (e != RCS_OK) return e;
+  std::vector<double> t((size_t)need);
+  e = rcs_state_export(s, t.data(), need, nullptr);
+  if (e != RCS_OK) return e;
+  const int32_t hdr[4] = {1, s->n, s->canonical ? 1 : 0, 0};
+  std::vector<int32_t> dims(s->dims.begin(), s->dims.end()), snake(s->pi.begin(), s->pi.end());
+  const std::string tmp_path = std::string(path) + ".tmp";
+  Fnv64 h;
+  {
+    FilePtr f(std::fopen(tmp_path.c_str(), "wb"));
+    if (!f) rcs::fail(RCS_ERR_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    auto put = [&](const void* p, size_t bytes) {
+      h.add(p, bytes);
+      if (std::fwrite(p, 1, bytes, f.get()) != bytes) rcs::fail(RCS_ERR_DEVICE, "write failed");
+    };
+    put(kMagic, 8);
+    put(hdr, sizeof(hdr));
+    put(&s->log_fest, sizeof(double));
+    put(dims.data(), dims.size() * sizeof(int32_t));
+    put(snake.data(), snake.size() * sizeof(int32_t));
+    put(t.data(), t.size() * sizeof(double));
+    const uint64_t sum = h.h;
+    if (std::fwrite(&sum, 1, 8, f.get()) != 8) rcs::fail(RCS_ERR_DEVICE, "write failed");
+    if (std::fflush(f.get()) != 0) rcs::fail(RCS_ERR_DEVICE, "write failed");
+  }
+  // the file appears complete or not at all
+  if (std::rename(tmp_path.c_str(), path) != 0) rcs::fail(RCS_ERR_DEVICE, "rename failed");
+  RCS_API_END
+}
+
+rcs_status rcs_state_load(const char* path, void* stream, rcs_state* out) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(path && out, "null argument");
+  *out = nullptr;
+  FilePtr f(std::fopen(path, "rb"));
+  if (!f) rcs::fail(RCS_ERR_INVALID_ARG, std::string("cannot open: ") + path);
+  Fnv64 h;
+  auto get = [&](void* p, size_t bytes) {
+    if (std::fread(p, 1, bytes, f.get()) != bytes) rcs::fail(RCS_ERR_INVALID_ARG, "truncated state file");
+    h.add(p, bytes);
+  };
+  char magic[8];
+  get(magic, 8);
+  RCS_REQUIRE(std::memcmp(magic, kMagic, 8) == 0, "not a state file (bad magic)");
+  int32_t hdr[4];
+  get(hdr, sizeof(hdr));
+  RCS_REQUIRE(hdr[0] == 1, "unsupported state file version");
+  const int n = hdr[1];
+  RCS_REQUIRE(n >= 1 && n <= 64, "bad qubit count in state file");
+  double log_fest = 0.0;
+  get(&log_fest, sizeof(double));
+  std::vector<int32_t> dims(n + 1), snake(n);
+  get(dims.data(), dims.size() * sizeof(int32_t));
+  get(snake.data(), snake.size() * sizeof(int32_t));
+  int64_t need = 0;
+  for (int k = 0; k < n; ++k) {
+    RCS_REQUIRE(dims[k] >= 1 && dims[k] <= 8192 && dims[k + 1] >= 1 && dims[k + 1] <= 8192,
+                "bond dimension out of range in state file");
+    need += (int64_t)dims[k] * 2 * dims[k + 1] * 2;
+  }
+  std::vector<double> t((size_t)need);
+  get(t.data(), t.size() * sizeof(double));
+  uint64_t sum = 0;
+  if (std::fread(&sum, 1, 8, f.get()) != 8) rcs::fail(RCS_ERR_INVALID_ARG, "truncated state file");
+  RCS_REQUIRE(sum == h.h, "state file checksum mismatch");
+  rcs_state st = nullptr;
+  const rcs_status e = rcs_state_import(n, dims.data(), snake.data(), t.data(), hdr[2], stream, &st);
+  if (e != RCS_OK) return e;
+  st->log_fest = log_fest;
+  *out = st;
   RCS_API_END
 }
 

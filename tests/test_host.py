@@ -138,3 +138,18 @@ def test_binding_without_the_library_raises(tmp_path):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError, match="librcs.so is not built"):
         spec.loader.exec_module(mod)
+
+
+def test_state_file_header_checks_need_no_gpu(rcs, tmp_path):
+    """rcs_state_load rejects files that are not state files before any
+    device work: bad magic, and a header cut short."""
+    p = tmp_path / "junk.mps"
+    p.write_bytes(b"NOTASTATEFILE" + bytes(64))
+    with pytest.raises(rcs.RcsError, match="magic") as ei:
+        rcs.State.load(str(p))
+    assert ei.value.status == 1
+    p.write_bytes(b"RCSMPS1\n" + bytes(6))
+    with pytest.raises(rcs.RcsError, match="truncated"):
+        rcs.State.load(str(p))
+    with pytest.raises(rcs.RcsError, match="cannot open"):
+        rcs.State.load(str(tmp_path / "missing.mps"))
