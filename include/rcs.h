@@ -306,6 +306,22 @@ rcs_status rcs_state_updates(rcs_state s, int32_t* n_updates, int32_t* records_h
 rcs_status rcs_state_rsvd_log(rcs_state s, int32_t* n_records, int64_t* n_values, int32_t* ints_host,
                               double* doubles_host, float* net_host, double* values_host);
 
+/* ------------------------------------------------------------ dense vector
+ * Section 5.1 scores samples by linear XEB against the circuit's exact
+ * output probabilities.  rcs_dense_simulate writes the exact output state
+ * of the circuit (same gates and order as the MPS build, no truncation) to
+ * psi_dev: 2^n complex128 amplitudes (n_amps = 2^n, caller-owned device
+ * memory, 256 GiB at 34 qubits), index i = sum_q b_q 2^q.  Work is ordered
+ * on `stream`.  Errors: INVALID_ARG for a null circuit or pointer, n above
+ * 36, n_amps != 2^n, or a coupler spanning 8 or more qubit numbers (grids
+ * up to 8 columns).
+ * rcs_dense_gather reads entries of such a vector at bitstrings bits_dev[0..m)
+ * (masked to n bits): out_dev[i] = psi[b_i] as complex128 (probabilities = 0)
+ * or |psi[b_i]|^2 as float64 (probabilities = 1), the reference for rcs_xeb. */
+rcs_status rcs_dense_simulate(rcs_circuit c, double* psi_dev, int64_t n_amps, void* stream);
+rcs_status rcs_dense_gather(const double* psi_dev, int32_t n_qubits, const uint64_t* bits_dev, uint64_t m,
+                            int32_t probabilities, double* out_dev, void* stream);
+
 /* -------------------------------------------------------- kernel-level calls
  * Exposed for parity tests of individual stages and for the training driver.
  * All device pointers, all ordered on `stream`. */

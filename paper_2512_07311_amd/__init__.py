@@ -97,6 +97,8 @@ _SIGS = {
     "rcs_state_updates": [_vp, _P(_i32), _P(_i32)],
     "rcs_state_rsvd_log": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d), _P(C.c_float), _P(_d)],
     "rcs_svd_jacobi": [_i32, _i32, _vp, _vp, _vp, _vp],
+    "rcs_dense_simulate": [_vp, _vp, _i64, _vp],
+    "rcs_dense_gather": [_vp, _i32, _vp, _u64, _i32, _vp, _vp],
     "rcs_cholqr": [_i32, _i32, _vp, _vp, _vp, _vp],
     "rcs_two_site": [_i32, _i32, _i32, _vp, _vp, _P(_d), _i32, _vp, _vp],
     "rcs_rsvd": [_i32, _i32, _vp, _i32, _i32, _u64, _u64, _vp, _P(_d), _vp],
@@ -406,6 +408,18 @@ def svd_jacobi(x, s, u, stream=None):
     len x cnt matrix); overwritten.  s: float64 (cnt,), u: complex128 like x."""
     cnt, ln = x.shape
     _check(_lib.rcs_svd_jacobi(ln, cnt, _ptr(x), _ptr(s), _ptr(u), _stream_ptr(stream)))
+
+
+def dense_simulate(circuit, psi, stream=None):
+    """psi: complex128 device tensor of 2^n entries, overwritten with the
+    circuit's exact output state (index bit q = qubit q)."""
+    _check(_lib.rcs_dense_simulate(circuit.h, _ptr(psi), psi.numel(), _stream_ptr(stream)))
+
+
+def dense_gather(psi, n_qubits, bits, out, probabilities=True, stream=None):
+    """out[i] = |psi[bits[i]]|^2 (float64) or psi[bits[i]] (complex128)."""
+    _check(_lib.rcs_dense_gather(_ptr(psi), n_qubits, _ptr(bits), bits.numel(), 1 if probabilities else 0,
+                                 _ptr(out), _stream_ptr(stream)))
 
 
 def cholqr(x, q, r, stream=None):

@@ -218,17 +218,37 @@ rcs_status rcs_state_import(int32_t n, const int32_t* dims_host, const int32_t* 
 namespace {
 constexpr char kMagic[8] = {'R', 'C', 'S', 'M', 'P', 'S', '1', '\n'};
 
+// FNV-1a over a byte stream taken as little-endian 64-bit words, the last
+// (length mod 8) bytes one at a time; add() may be called with any split
+// of the stream.
 struct Fnv64 {
   uint64_t h = 1469598103934665603ull;
+  unsigned char pend[8];
+  int np = 0;
+  void word(uint64_t w) { h = (h ^ w) * 1099511628211ull; }
   void add(const void* p, size_t bytes) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
     size_t i = 0;
+    while (np > 0 && i < bytes) {
+      pend[np++] = c[i++];
+      if (np == 8) {
+        uint64_t w;
+        std::memcpy(&w, pend, 8);
+        word(w);
+        np = 0;
+      }
+    }
     for (; i + 8 <= bytes; i += 8) {
       uint64_t w;
       std::memcpy(&w, c + i, 8);
-      h = (h ^ w) * 1099511628211ull;
+      word(w);
     }
-    for (; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    for (; i < bytes; ++i) pend[np++] = c[i];
+  }
+  uint64_t finish() {
+    for (int i = 0; i < np; ++i) h = (h ^ pend[i]) * 1099511628211ull;
+    np = 0;
+    return h;
   }
 };
 
@@ -266,7 +286,7 @@ rcs_status rcs_state_save(rcs_state s, const char* path) {
     put(dims.data(), dims.size() * sizeof(int32_t));
     put(snake.data(), snake.size() * sizeof(int32_t));
     put(t.data(), t.size() * sizeof(double));
-    const uint64_t sum = h.h;
+    const uint64_t sum = h.finish();
     if (std::fwrite(&sum, 1, 8, f.get()) != 8) rcs::fail(RCS_ERR_DEVICE, "write failed");
     if (std::fflush(f.get()) != 0) rcs::fail(RCS_ERR_DEVICE, "write failed");
   }
@@ -309,7 +329,7 @@ rcs_status rcs_state_load(const char* path, void* stream, rcs_state* out) {
   get(t.data(), t.size() * sizeof(double));
   uint64_t sum = 0;
   if (std::fread(&sum, 1, 8, f.get()) != 8) rcs::fail(RCS_ERR_INVALID_ARG, "truncated state file");
-  RCS_REQUIRE(sum == h.h, "state file checksum mismatch");
+  RCS_REQUIRE(sum == h.finish(), "state file checksum mismatch");
   rcs_state st = nullptr;
   const rcs_status e = rcs_state_import(n, dims.data(), snake.data(), t.data(), hdr[2], stream, &st);
   if (e != RCS_OK) return e;
