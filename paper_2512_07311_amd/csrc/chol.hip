@@ -65,115 +65,85 @@ __device__ inline double2 cmul_hc(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// In-LDS Cholesky of the Hermitian 64 x 64 block T (upper part used):
-// T <- R with T = R^H R.  A pivot that is not positive and finite sets
-// *flag and is replaced by 1 (the result is then discarded by the caller).
-__device__ void chol64_lds(double2 (*T)[CB + 1], int* flag) {
-  __shared__ double inv_piv;
-  const int tid = threadIdx.x;
-  for (int k = 0; k < CB; ++k) {
-    if (tid == 0) {
-      double d = T[k][k].x;
-      if (!(d > 0.0) || !(d < 1e300)) {
-        atomicExch(flag, 1);
-        d = 1.0;
-      }
-      const double r = sqrt(d);
-      T[k][k] = make_double2(r, 0.0);
-      inv_piv = 1.0 / r;
-    }
-    __syncthreads();
-    for (int c = k + 1 + tid; c < CB; c += CHOL_THREADS) {
-      const double2 v = T[k][c];
-      T[k][c] = make_double2(v.x * inv_piv, v.y * inv_piv);
-    }
-    __syncthreads();
-    const int m = CB - 1 - k;                    // trailing size
-    for (int e = tid; e < m * m; e += CHOL_THREADS) {
-      const int r = k + 1 + e / m, c = k + 1 + e % m;
-      if (r <= c) {
-        const double2 p = cmul_hc(T[k][r], T[k][c]);
-        T[r][c] = make_double2(T[r][c].x - p.x, T[r][c].y - p.y);
-      }
-    }
-    __syncthreads();
-  }
-}
+// Panel jb, one wavefront per workgroup, lane c owning column c of the
+// 64 x 64 blocks in LDS:
+//  * every workgroup factors the diagonal block G_jj = R^H R (right-looking;
+//    at step k every lane reads the pivot, lanes c > k scale R[k][c] and then
+//    update their column's entries T[r][c], k < r <= c, with the broadcast
+//    row k); a pivot that is not positive and finite sets *flag;
+//  * workgroup 0 stores R_jj (column-major in Rd) and, when Ri is given, the
+//    diagonal block of R^{-1} (lane c back-substitutes column c of R^{-1});
+//  * workgroup t >= 1 solves its tile of the block row, R_jt = R^{-H} G_jt,
+//    by forward substitution, lane c on column c.
+constexpr int PANEL_THREADS = 64;
 
-// In-place inverse of the upper-triangular T (64 x 64): columns left to
-// right, T[0:j, j] <- -T[0:j,0:j]^{-1}-part times the old column / T[j][j],
-// using the already inverted leading block.
-__device__ void trinv64_lds(double2 (*T)[CB + 1]) {
-  __shared__ double2 col[CB];
-  const int tid = threadIdx.x;
-  for (int j = 0; j < CB; ++j) {
-    // inverse diagonal entry (real positive)
-    const double djj = 1.0 / T[j][j].x;
-    // new column entries i < j: -djj * sum_{m=i}^{j-1} Tinv[i][m] T[m][j]
-    if (tid < j) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int m = tid; m < j; ++m) {
-        const double2 p = cmul_c(T[tid][m], T[m][j]);
-        s.x += p.x;
-        s.y += p.y;
-      }
-      col[tid] = make_double2(-djj * s.x, -djj * s.y);
-    }
-    __syncthreads();
-    if (tid < j) T[tid][j] = col[tid];
-    if (tid == 0) T[j][j] = make_double2(djj, 0.0);
-    __syncthreads();
-  }
-}
-
-// Panel jb: diagonal factor (all workgroups), R_jj store (workgroup 0),
-// block-row solve R_jt = R_jj^{-H} G_jt (workgroup t, tile jb + t).
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd,
-                                                             double2* Ri) {
+__global__ __launch_bounds__(PANEL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd,
+                                                              double2* Ri) {
   __shared__ double2 T[CB][CB + 1];
   __shared__ double2 A[CB][CB + 1];
-  const int tid = threadIdx.x;
+  const int c = threadIdx.x;
   const int j0 = jb * CB;
-  for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
-    const int r = e % CB, c = e / CB;
-    T[r][c] = G[(int64_t)(j0 + c) * ldg + j0 + r];
-  }
+  for (int cc = 0; cc < CB; ++cc) T[c][cc] = G[(int64_t)(j0 + cc) * ldg + j0 + c];
   __syncthreads();
-  chol64_lds(T, flag);
+  for (int k = 0; k < CB; ++k) {
+    double d = T[k][k].x;
+    const bool bad = !(d > 0.0) || !(d < 1e300);
+    if (bad) d = 1.0;
+    if (bad && c == 0) atomicExch(flag, 1);
+    const double r = sqrt(d), inv = 1.0 / r;
+    __syncthreads();                      // the pivot is read before it is overwritten
+    if (c == k) T[k][k] = make_double2(r, 0.0);
+    if (c > k) T[k][c] = make_double2(T[k][c].x * inv, T[k][c].y * inv);
+    __syncthreads();
+    if (c > k) {
+      const double2 rc = T[k][c];
+      for (int rr = k + 1; rr <= c; ++rr) {
+        const double2 p = cmul_hc(T[k][rr], rc);
+        T[rr][c] = make_double2(T[rr][c].x - p.x, T[rr][c].y - p.y);
+      }
+    }
+    __syncthreads();
+  }
   if (blockIdx.x == 0) {
     double2* rd = Rd + (int64_t)jb * CB * CB;
-    for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
-      const int r = e % CB, c = e / CB;
-      rd[e] = r <= c ? T[r][c] : make_double2(0.0, 0.0);
-    }
+    for (int cc = 0; cc < CB; ++cc) rd[cc * CB + c] = c <= cc ? T[c][cc] : make_double2(0.0, 0.0);
     if (Ri) {
-      // diagonal block of R^{-1} (ld ldg)
-      __syncthreads();
-      trinv64_lds(T);
-      for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
-        const int r = e % CB, c = e / CB;
-        Ri[(int64_t)(j0 + c) * ldg + j0 + r] = r <= c ? T[r][c] : make_double2(0.0, 0.0);
+      // column c of R^{-1}: x_c = 1 / R_cc; x_i = -(sum_{m=i+1}^{c} R_im x_m) / R_ii, i < c
+      A[c][c] = make_double2(1.0 / T[c][c].x, 0.0);
+      for (int i = CB - 2; i >= 0; --i) {
+        if (c > i) {
+          double2 sum = make_double2(0.0, 0.0);
+          for (int m = i + 1; m <= c; ++m) {
+            const double2 p = cmul_c(T[i][m], A[m][c]);
+            sum.x += p.x;
+            sum.y += p.y;
+          }
+          const double q = -1.0 / T[i][i].x;
+          A[i][c] = make_double2(q * sum.x, q * sum.y);
+        }
       }
+      __syncthreads();
+      for (int cc = 0; cc < CB; ++cc)
+        Ri[(int64_t)(j0 + cc) * ldg + j0 + c] = c <= cc ? A[c][cc] : make_double2(0.0, 0.0);
     }
     return;
   }
-  const int t0 = j0 + blockIdx.x * CB;           // first column of this tile
-  for (int e = tid; e < CB * CB; e += CHOL_THREADS) {
-    const int r = e % CB, c = e / CB;
-    A[r][c] = G[(int64_t)(t0 + c) * ldg + j0 + r];
-  }
-  trinv64_lds(T);                                 // T <- R_jj^{-1} (upper)
-  // out[r][c] = sum_{m <= r} conj(Rinv[m][r]) A[m][c]
-  const int c = tid & (CB - 1);
-  for (int r = tid >> 6; r < CB; r += CHOL_THREADS / CB) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int m = 0; m <= r; ++m) {
-      const double2 p = cmul_hc(T[m][r], A[m][c]);
-      s.x += p.x;
-      s.y += p.y;
+  const int t0 = j0 + blockIdx.x * CB;    // first column of this tile
+  for (int cc = 0; cc < CB; ++cc) A[c][cc] = G[(int64_t)(t0 + cc) * ldg + j0 + c];
+  __syncthreads();
+  // R^H X = A, column c: X_i = (A_i - sum_{m<i} conj(R_mi) X_m) / R_ii
+  for (int i = 0; i < CB; ++i) {
+    double2 sum = A[i][c];
+    for (int m = 0; m < i; ++m) {
+      const double2 p = cmul_hc(T[m][i], A[m][c]);
+      sum.x -= p.x;
+      sum.y -= p.y;
     }
-    G[(int64_t)(t0 + c) * ldg + j0 + r] = s;
+    const double q = 1.0 / T[i][i].x;
+    A[i][c] = make_double2(q * sum.x, q * sum.y);
   }
+  __syncthreads();
+  for (int cc = 0; cc < CB; ++cc) G[(int64_t)(t0 + cc) * ldg + j0 + c] = A[c][cc];
 }
 
 // Trailing update after panel jb: tile (ti, tj), jb < ti <= tj < nb:
@@ -233,7 +203,7 @@ static void gram_cholesky(const double2* X, int ldx, int len, int n, double2* G,
   hipLaunchKernelGGL(k_gram_upper, dim3(nb, nb), dim3(GT_THREADS), 0, s, X, ldx, len, n, G, ldg);
   HIP_LAUNCH_OK();
   for (int jb = 0; jb < nb; ++jb) {
-    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(CHOL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd, Ri);
+    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(PANEL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd, Ri);
     HIP_LAUNCH_OK();
     const int T = nb - jb - 1;
     if (T > 0) {
@@ -317,11 +287,14 @@ void cholqr(const double2* X, int ldx, int len, int n, double2* G, int ldg, doub
   cgemm_cm(X, ldx, 0, Ri, ldg, 0, Q, ldq, 0, len, n, n, 1.0, 1, s);
 }
 
-// *dev = max over entries of |H - I| (H k x k, row-major), one workgroup.
+// *dev = max over entries of |H - I| (H k x k, row-major); *dev must be 0
+// beforehand.  Non-negative doubles order like their bit patterns, so the
+// workgroups combine with an integer atomic max.
 __global__ void k_max_dev_identity(const double2* H, int k, double* dev) {
   __shared__ double red[256];
   double m = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += 256) {
+  const int64_t tot = (int64_t)k * k;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
     const int r = (int)(e / k), c = (int)(e % k);
     const double2 h = H[e];
     const double re = h.x - (r == c ? 1.0 : 0.0);
@@ -334,11 +307,15 @@ __global__ void k_max_dev_identity(const double2* H, int k, double* dev) {
     if ((int)threadIdx.x < h2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h2]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *dev = red[0];
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(dev), (unsigned long long)__double_as_longlong(red[0]));
 }
 
 void max_dev_identity(const double2* H, int k, double* dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_max_dev_identity, dim3(1), dim3(256), 0, s, H, k, dev);
+  HIP_OK(hipMemsetAsync(dev, 0, sizeof(double), s));
+  const int64_t tot = (int64_t)k * k;
+  const int blocks = (int)std::min<int64_t>(1024, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_max_dev_identity, dim3(std::max(blocks, 1)), dim3(256), 0, s, H, k, dev);
   HIP_LAUNCH_OK();
 }
 
