@@ -20,6 +20,22 @@ a seed under these readings:
 * cycle t: single-qubit layer on every qubit, then fSim on every coupler of
   pattern[t mod len(pattern)]; after the last cycle one more single-qubit
   layer (drawn at t = n_cycles) when final_layer is set.
+
+A second lattice ("rotated") stands in for Sycamore's rotated square
+lattice, where every qubit couples to up to four diagonal neighbours, two in
+the row above and two in the row below, and the coupler patterns are
+labelled A-H (Section 3.1 runs ABCDCDAB and EFGH).  Google's layout files
+are not available, so the lattice and the patterns are a reading:
+* couplers join adjacent rows only: "down-left" (r,c)-(r+1,c) and
+  "down-right" (r,c)-(r+1,c+s) with s = +1 on even rows and -1 on odd rows,
+  so each site has two neighbours below and two above;
+* A, B: down-left couplers with r even / odd; C, D: down-right couplers
+  with r even / odd (row-parity stripes);
+* E, F: down-left couplers with r - c even / odd; G, H: down-right
+  couplers with r - ch even / odd, ch = c on even rows and c - 1 on odd
+  rows (the column of the coupler's chain: down-right couplers chain
+  (r, c) -> (r+1, c+s) -> (r+2, c)), a staggered split;
+* every pattern is a matching, A-D and E-H each cover every coupler once.
 """
 import math
 import numpy as np
@@ -53,7 +69,10 @@ class Circuit:
 
     def __init__(self, rows, cols, n_cycles, seed, pattern="ABCDCDAB",
                  removed=None, n_removed_random=0, theta=math.pi / 2,
-                 phi=math.pi / 6, final_layer=True):
+                 phi=math.pi / 6, final_layer=True, lattice="rect"):
+        if lattice not in ("rect", "rotated"):
+            raise ValueError("lattice is 'rect' or 'rotated'")
+        self.lattice = lattice
         self.rows, self.cols = int(rows), int(cols)
         self.W = min(self.rows, self.cols)
         self.H = max(self.rows, self.cols)
@@ -83,6 +102,8 @@ class Circuit:
 
     def couplers(self, letter):
         """Couplers (qa, qb) of pattern letter, qa < qb as qubit ids."""
+        if self.lattice == "rotated":
+            return self._rotated_couplers(letter)
         out = []
         for r in range(self.H):
             for c in range(self.W):
@@ -96,6 +117,29 @@ class Circuit:
                     a, b = self.site(r, c), self.site(r + 1, c)
                 else:
                     raise ValueError("pattern letters are A, B, C, D")
+                if a in self.qubit_of_site and b in self.qubit_of_site:
+                    out.append((self.qubit_of_site[a], self.qubit_of_site[b]))
+        return out
+
+    def _rotated_couplers(self, letter):
+        if letter not in "ABCDEFGH":
+            raise ValueError("rotated-lattice pattern letters are A-H")
+        down_left = letter in "ABEF"
+        out = []
+        for r in range(self.H - 1):
+            for c in range(self.W):
+                shift = 0 if down_left else (1 if r % 2 == 0 else -1)
+                c2 = c + shift
+                if not 0 <= c2 < self.W:
+                    continue
+                if letter in "ABCD":
+                    parity = r % 2
+                else:
+                    chain = c if (down_left or r % 2 == 0) else c - 1
+                    parity = (r - chain) % 2
+                if parity != (0 if letter in "ACEG" else 1):
+                    continue
+                a, b = self.site(r, c), self.site(r + 1, c2)
                 if a in self.qubit_of_site and b in self.qubit_of_site:
                     out.append((self.qubit_of_site[a], self.qubit_of_site[b]))
         return out

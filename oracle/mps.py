@@ -28,7 +28,10 @@ step below is the plain textbook operation, in complex128 with numpy/LAPACK:
   left (in column order); odd cycles go right to left and move top qubits
   right (in reverse column order).  A full row pair costs W^2 updates
   (W(W-1)/2 SWAPs each way plus W gates) against 2W(W-1) + W for the base
-  network on the snake order;
+  network on the snake order.  On the rotated lattice every layer is made of
+  row pairs (the rows holding the layer's couplers), and a bottom qubit's
+  key uses its column minus the pair's coupler offset (0, or +-1 for
+  down-right couplers), so that it sorts just after its partner;
 * update(i, G): move the orthogonality centre into {i, i+1} with exact QR/LQ
   steps; theta = A_i A_{i+1}; theta' = G on (s1, s2); M = theta' as a
   (2 chi_l) x (2 chi_r) matrix with rows (s1, a) and columns (s2, c); SVD;
@@ -103,7 +106,7 @@ def _schedule_interleaved(circ):
             continue
         letter = circ.pattern[t % len(circ.pattern)]
         right_to_left = (t % 2 == 1)
-        if letter in "AB":
+        if circ.lattice == "rect" and letter in "AB":
             # horizontal neighbours are neighbouring positions
             for a, b in sorted(data, reverse=right_to_left):
                 i, j = sorted((pi.index(a), pi.index(b)))
@@ -111,8 +114,11 @@ def _schedule_interleaved(circ):
                 ops.append(("u", i, "fsim", t))
         else:
             coupled = set(data)
-            first_row = 0 if letter == "C" else 1
-            row_pairs = list(range(first_row, circ.H - 1, 2))
+            if circ.lattice == "rect":
+                first_row = 0 if letter == "C" else 1
+                row_pairs = list(range(first_row, circ.H - 1, 2))
+            else:
+                row_pairs = sorted({circ.present[a] // circ.W for a, _ in data})
             if right_to_left:
                 row_pairs.reverse()
             for r in row_pairs:
@@ -120,11 +126,18 @@ def _schedule_interleaved(circ):
                        if circ.site(r, c) in circ.qubit_of_site]
                 bot = [circ.qubit_of_site[circ.site(r + 1, c)] for c in range(circ.W)
                        if circ.site(r + 1, c) in circ.qubit_of_site]
+                # column offset of this row pair's couplers (bottom minus top):
+                # 0 for vertical couplers, +-1 for the rotated lattice's
+                # down-right ones; a bottom qubit sorts just after its partner
+                offsets = {circ.present[b] % circ.W - circ.present[a] % circ.W
+                           for a, b in data if circ.present[a] // circ.W == r}
+                assert len(offsets) <= 1
+                delta = offsets.pop() if offsets else 0
                 key = {}
                 for q in top:
                     key[q] = 2 * (circ.present[q] % circ.W)
                 for q in bot:
-                    key[q] = 2 * (circ.present[q] % circ.W) + 1
+                    key[q] = 2 * (circ.present[q] % circ.W - delta) + 1
                 block = [pi.index(q) for q in top + bot]
                 start, end = min(block), max(block)
                 swaps = []

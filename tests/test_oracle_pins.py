@@ -295,6 +295,58 @@ def test_interleaved_network_53_qubit_counts():
             assert sum(1 for o in mps.schedule(c, net)[1] if o[0] == "u") == want
 
 
+def test_rotated_lattice_patterns():
+    """Rotated lattice (the Sycamore stand-in): every pattern A-H is a
+    matching; A-D and E-H each cover the same couplers, every one once;
+    interior sites have two neighbours in the row above and two below, and
+    every coupler joins adjacent rows."""
+    c = Circuit(6, 9, 1, 1, lattice="rotated")
+    nbrs = {q: set() for q in range(c.n)}
+    covers = []
+    for group in ("ABCD", "EFGH"):
+        seen = []
+        for letter in group:
+            cp = c.couplers(letter)
+            qs = [q for e in cp for q in e]
+            assert len(qs) == len(set(qs)), letter
+            seen += [tuple(sorted(e)) for e in cp]
+        assert len(seen) == len(set(seen))
+        covers.append(set(seen))
+    assert covers[0] == covers[1] and len(covers[0]) == 6 * 8 + 5 * 8
+    for a, b in covers[0]:
+        ra, rb = c.present[a] // c.W, c.present[b] // c.W
+        assert rb == ra + 1 and abs(c.present[b] % c.W - c.present[a] % c.W) <= 1
+        nbrs[a].add(b)
+        nbrs[b].add(a)
+    for r in range(1, c.H - 1):
+        for col in range(1, c.W - 1):
+            q = c.qubit_of_site[c.site(r, col)]
+            rows = sorted(c.present[x] // c.W for x in nbrs[q])
+            assert rows == [r - 1, r - 1, r + 1, r + 1]
+
+
+@pytest.mark.parametrize("network", ["snake", "interleaved"])
+@pytest.mark.parametrize("rows,cols,cyc,pattern,removed", [(3, 4, 8, "ABCDCDAB", None), (4, 4, 8, "EFGH", None),
+                                                           (4, 4, 10, "ABCDCDAB", [6]), (3, 5, 8, "GHEF", None)])
+def test_rotated_lattice_exact_mps_equals_dense(network, rows, cols, cyc, pattern, removed):
+    c = Circuit(rows, cols, cyc, seed=3, pattern=pattern, removed=removed, lattice="rotated")
+    st = mps.build(c, 1 << (c.n // 2), 0.0, network=network)
+    assert np.abs(st.to_dense() - dense.simulate(c)).max() <= 1e-12 * 2.0 ** (-c.n / 2)
+
+
+@pytest.mark.parametrize("pattern", ["ABCDCDAB", "EFGH"])
+def test_rotated_lattice_interleaved_gates_and_order(pattern):
+    """Each cycle's fSim updates act on exactly that cycle's couplers, and
+    the row-major order holds at every layer boundary (rotated lattice,
+    53 qubits)."""
+    c = Circuit(6, 9, 14, seed=1, pattern=pattern, n_removed_random=1, lattice="rotated")
+    pi, ops = mps.schedule(c, "interleaved")
+    gates, orders = _replay_labels(c, ops, pi)
+    for t in range(c.n_cycles):
+        assert sorted(gates.get(t, [])) == sorted(tuple(sorted(e)) for e in c.layers[2 * t + 1][1])
+        assert orders[t + 1] == list(range(c.n))
+
+
 def test_single_truncation_fidelity_is_one_minus_eps():
     c = Circuit(3, 4, 8, seed=3)
     psi = dense.simulate(c)
