@@ -62,6 +62,14 @@ typedef enum {
  *   optional final single-qubit layer.
  * All draws come from Philox4x32-10 keyed by the seed (counter layout in
  * the library's design notes); the same desc always gives the same circuit.
+ * Rotated lattice (lattice = 1), the stand-in for Sycamore's rotated square
+ * lattice and its patterns A-H (Google's layout files are not available, so
+ * this is a reading): couplers only between adjacent rows, down-left
+ * (r,c)-(r+1,c) and down-right (r,c)-(r+1,c+s), s = +1 on even rows and -1
+ * on odd rows; A/B = down-left with r even/odd, C/D = down-right with r
+ * even/odd, E/F = down-left with r-c even/odd, G/H = down-right with r-ch
+ * even/odd (ch = c on even rows, c-1 on odd rows).  Each pattern is a
+ * matching; A-D and E-H each cover every coupler once.
  */
 typedef struct {
   int32_t rows, cols;             /* grid, 2 <= rows, cols; rows*cols <= 4096 */
@@ -75,6 +83,8 @@ typedef struct {
   int32_t final_1q_layer;         /* 1: one more single-qubit layer at end    */
   int32_t swap_network;           /* MPS order and swap network (0 or 1):     */
                                   /* 0 snake, 1 interleaved row pairs         */
+  int32_t lattice;                /* 0 rectangular (patterns A-D above);      */
+                                  /* 1 rotated, patterns A-H (below)          */
 } rcs_circuit_desc;
 
 /* Validates and generates the circuit and its MPS schedule (host only, no

@@ -27,6 +27,7 @@ RCS_PREC_C128, RCS_PREC_C64, RCS_PREC_SPLIT_BF16 = 0, 1, 2
 RCS_RANK_FULL_SVD, RCS_RANK_LEARNED, RCS_RANK_RSVD_AT_CAP = 0, 1, 2
 PRECISIONS = {"c128": 0, "c64": 1, "split_bf16": 2}
 NETWORKS = {"snake": 0, "interleaved": 1}
+LATTICES = {"rect": 0, "rotated": 1}
 MLP_PARAMS = 66 * 128 + 128 + 128 * 128 + 128 + 128 * 32 + 32
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
@@ -44,7 +45,7 @@ class CircuitDesc(C.Structure):
                 ("seed", C.c_uint64), ("n_removed", C.c_int32),
                 ("removed_sites", C.POINTER(C.c_int32)), ("n_removed_random", C.c_int32),
                 ("pattern", C.c_char_p), ("theta", C.c_double), ("phi", C.c_double),
-                ("final_1q_layer", C.c_int32), ("swap_network", C.c_int32)]
+                ("final_1q_layer", C.c_int32), ("swap_network", C.c_int32), ("lattice", C.c_int32)]
 
 
 class BuildOpts(C.Structure):
@@ -165,13 +166,14 @@ def _stream_ptr(stream):
 class Circuit:
     def __init__(self, rows, cols, n_cycles, seed, pattern="ABCDCDAB", removed=(),
                  n_removed_random=0, theta=np.pi / 2, phi=np.pi / 6, final_1q_layer=True,
-                 network="snake"):
+                 network="snake", lattice="rect"):
         rem = (C.c_int32 * max(1, len(removed)))(*removed)
         self._pattern = pattern.encode() if pattern is not None else None
         self.network = network
         d = CircuitDesc(rows, cols, n_cycles, seed & 0xFFFFFFFFFFFFFFFF, len(removed),
                         C.cast(rem, _P(C.c_int32)), n_removed_random, self._pattern,
-                        float(theta), float(phi), 1 if final_1q_layer else 0, NETWORKS[network])
+                        float(theta), float(phi), 1 if final_1q_layer else 0, NETWORKS[network],
+                        LATTICES[lattice])
         h = C.c_void_p()
         _check(_lib.rcs_circuit_create(C.byref(d), C.byref(h)))
         self.h = h

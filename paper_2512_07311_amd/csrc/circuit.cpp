@@ -101,7 +101,7 @@ static void compile_interleaved(rcs_circuit_s& c) {
     const char letter = c.pattern[t % c.pattern.size()];
     const bool leftward = (t % 2) == 1;     // odd cycles run right to left
     const auto& cp = c.layers_2q[t];
-    if (letter == 'A' || letter == 'B') {
+    if (c.lattice == 0 && (letter == 'A' || letter == 'B')) {
       std::vector<int> left;
       for (auto& e : cp) {
         const int a = std::min(e.first, e.second), b = std::max(e.first, e.second);
@@ -120,9 +120,27 @@ static void compile_interleaved(rcs_circuit_s& c) {
       partner_above[b] = a;
     }
     std::vector<int> row_pairs;
-    for (int r = (letter == 'C' ? 0 : 1); r + 1 < c.H; r += 2) row_pairs.push_back(r);
+    if (c.lattice == 0) {
+      for (int r = (letter == 'C' ? 0 : 1); r + 1 < c.H; r += 2) row_pairs.push_back(r);
+    } else {
+      // the rows holding the layer's couplers (as top rows), ascending
+      for (auto& e : cp) row_pairs.push_back(row_of[std::min(e.first, e.second)]);
+      std::sort(row_pairs.begin(), row_pairs.end());
+      row_pairs.erase(std::unique(row_pairs.begin(), row_pairs.end()), row_pairs.end());
+    }
     if (leftward) std::reverse(row_pairs.begin(), row_pairs.end());
     for (int r : row_pairs) {
+      // column offset (bottom minus top) of this row pair's couplers
+      int delta = 0;
+      bool have = false;
+      for (auto& e : cp) {
+        const int a = std::min(e.first, e.second), b = std::max(e.first, e.second);
+        if (row_of[a] != r) continue;
+        const int dlt = col_of[b] - col_of[a];
+        RCS_REQUIRE(!have || dlt == delta, "row pair with mixed coupler offsets");
+        delta = dlt;
+        have = true;
+      }
       // block [lo, hi): the present qubits of rows r and r+1 (contiguous)
       int lo = n, hi = 0;
       for (int q = 0; q < n; ++q)
@@ -131,7 +149,7 @@ static void compile_interleaved(rcs_circuit_s& c) {
           hi = std::max(hi, q + 1);
         }
       if (lo >= hi) continue;
-      auto key = [&](int q) { return 2 * col_of[q] + (row_of[q] == r + 1 ? 1 : 0); };
+      auto key = [&](int q) { return row_of[q] == r + 1 ? 2 * (col_of[q] - delta) + 1 : 2 * col_of[q]; };
       std::vector<int> walk;                      // SWAP positions, in order
       auto where = [&](int q) { return (int)(std::find(order.begin() + lo, order.begin() + hi, q) - order.begin()); };
       if (!leftward) {
@@ -186,7 +204,11 @@ void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
   c.seed = d.seed;
   c.pattern = d.pattern ? std::string(d.pattern) : std::string("ABCDCDAB");
   RCS_REQUIRE(!c.pattern.empty(), "empty pattern");
-  for (char ch : c.pattern) RCS_REQUIRE(ch >= 'A' && ch <= 'D', "pattern letters must be A-D");
+  RCS_REQUIRE(d.lattice == 0 || d.lattice == 1, "lattice must be 0 (rectangular) or 1 (rotated)");
+  c.lattice = d.lattice;
+  for (char ch : c.pattern)
+    RCS_REQUIRE(ch >= 'A' && ch <= (c.lattice == 1 ? 'H' : 'D'),
+                c.lattice == 1 ? "pattern letters must be A-H" : "pattern letters must be A-D");
   c.theta = d.theta;
   c.phi = d.phi;
   c.final_layer = d.final_1q_layer != 0;
@@ -216,6 +238,28 @@ void generate_circuit(const rcs_circuit_desc& d, rcs_circuit_s& c) {
 
   auto couplers = [&](char letter) {
     std::vector<std::pair<int, int>> out;
+    if (c.lattice == 1) {
+      // rotated lattice: down-left (r,c)-(r+1,c) for A, B, E, F and
+      // down-right (r,c)-(r+1,c+s), s = +1 on even rows, -1 on odd rows, for
+      // C, D, G, H; A-D select by row parity, E-H by r minus the coupler
+      // chain's column (c, or c-1 for down-right couplers from odd rows)
+      const bool down_left = letter == 'A' || letter == 'B' || letter == 'E' || letter == 'F';
+      const bool stripes = letter <= 'D';
+      const int want = (letter == 'A' || letter == 'C' || letter == 'E' || letter == 'G') ? 0 : 1;
+      for (int r = 0; r + 1 < c.H; ++r)
+        for (int col = 0; col < c.W; ++col) {
+          const int shift = down_left ? 0 : (r % 2 == 0 ? 1 : -1);
+          const int col2 = col + shift;
+          if (col2 < 0 || col2 >= c.W) continue;
+          const int chain = (down_left || r % 2 == 0) ? col : col - 1;
+          const int parity = stripes ? (r % 2) : (((r - chain) % 2) + 2) % 2;
+          if (parity != want) continue;
+          const int a = r * c.W + col, b = (r + 1) * c.W + col2;
+          if (c.qubit_of_site[a] >= 0 && c.qubit_of_site[b] >= 0)
+            out.emplace_back(c.qubit_of_site[a], c.qubit_of_site[b]);
+        }
+      return out;
+    }
     for (int r = 0; r < c.H; ++r)
       for (int col = 0; col < c.W; ++col) {
         int a, b;

@@ -29,6 +29,7 @@ struct rcs_circuit_s {
   std::vector<std::vector<int>> layers_1q;               // gate index per qubit
   std::vector<std::vector<std::pair<int, int>>> layers_2q; // couplers (qubit ids)
   int network = 0;                     // 0 snake, 1 interleaved row pairs
+  int lattice = 0;                     // 0 rectangular, 1 rotated (couplers between adjacent rows)
   std::vector<int> snake;              // position -> qubit at the start
   std::vector<Op> ops;
   int n_updates = 0;

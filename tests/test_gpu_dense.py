@@ -36,6 +36,15 @@ def test_dense_matches_oracle(env, rows, cols, cyc, seed, removed):
     assert np.abs(psi - ref).max() <= 1e-12 * 2.0 ** (-c.n / 2)
 
 
+@pytest.mark.parametrize("pattern", ["ABCDCDAB", "EFGH"])
+def test_dense_rotated_lattice_matches_oracle(env, pattern):
+    rcs, torch = env
+    c = rcs.Circuit(4, 5, 10, 2, pattern=pattern, removed=(7,), lattice="rotated")
+    psi = _dense_gpu(rcs, torch, c).cpu().numpy()
+    ref = dense.simulate(oc.Circuit(4, 5, 10, 2, pattern=pattern, removed=[7], lattice="rotated"))
+    assert np.abs(psi - ref).max() <= 1e-12 * 2.0 ** (-c.n / 2)
+
+
 def test_dense_gather(env):
     rcs, torch = env
     c = rcs.Circuit(3, 4, 8, 1)

@@ -153,3 +153,29 @@ def test_state_file_header_checks_need_no_gpu(rcs, tmp_path):
         rcs.State.load(str(p))
     with pytest.raises(rcs.RcsError, match="cannot open"):
         rcs.State.load(str(tmp_path / "missing.mps"))
+
+
+@pytest.mark.parametrize("network", ["snake", "interleaved"])
+@pytest.mark.parametrize("rows,cols,cyc,rr,pattern", [(6, 9, 14, 1, "ABCDCDAB"), (6, 9, 14, 1, "EFGH"),
+                                                      (6, 9, 20, 1, "ABCDCDAB"), (4, 5, 9, 0, "GHEFDCBA"),
+                                                      (3, 4, 8, 0, "EFGH")])
+def test_rotated_lattice_schedule_matches_oracle(rcs, rows, cols, cyc, rr, pattern, network):
+    """The rotated-lattice circuits (couplers, gate draws, schedule) equal the
+    oracle's op by op, for both networks."""
+    c = rcs.Circuit(rows, cols, cyc, 7, pattern=pattern, n_removed_random=rr, network=network, lattice="rotated")
+    o = OCircuit(rows, cols, cyc, 7, pattern=pattern, n_removed_random=rr, lattice="rotated")
+    assert c.n == o.n
+    assert np.array_equal(c.one_qubit_gates(), o.one_qubit_draws())
+    snake, ops = c.schedule()
+    pi, oops = omps.schedule(o, network)
+    assert list(snake) == pi
+    assert [tuple(x[1:3]) if x[0] == 1 else (x[3],) for x in ops] == \
+        [(op[1], 0 if op[2] == "fsim" else 1) if op[0] == "u" else (op[2],) for op in oops]
+
+
+def test_rotated_lattice_pattern_letters(rcs):
+    with pytest.raises(rcs.RcsError, match="A-D"):
+        rcs.Circuit(3, 3, 2, 1, pattern="ABE")
+    rcs.Circuit(3, 3, 2, 1, pattern="ABEH", lattice="rotated")
+    with pytest.raises(rcs.RcsError, match="A-H"):
+        rcs.Circuit(3, 3, 2, 1, pattern="ABI", lattice="rotated")
