@@ -70,7 +70,7 @@ def log(msg):
 # the source file of each probed kernel class (its hash ties counter data to
 # the kernel version it was taken on)
 KERNEL_SOURCE = {"k_chain_gemm": "sample.hip", "k_jac_gram": "jacobi.hip", "k_jac_rotate": "jacobi.hip",
-                 "k_two_site": "build.hip", "k_range_finder": "rsvd.hip"}
+                 "k_two_site": "build.hip", "k_range_finder": "rsvd.hip", "k_factor_other": "chol.hip"}
 
 
 def source_hash(kernel):
@@ -220,15 +220,16 @@ def main_batch(args, wl):
 
 
 def svd_roofline(prof, inf, floor_s, steps):
-    """Roofline of the fp64 factorisation kernels (the Jacobi Gram and
-    rotation passes, which together do every SVD and centre move of the
-    build): algorithmic work = the nominal flops of those factorisations
-    (thin SVD 4 (14 m n^2 + 8 n^3) per update, Householder QR
-    4 (2 m n^2 - 2 n^3 / 3) per centre move); time = each class's probed
-    average launch time, less the event floor, times its launches."""
+    """Roofline of the fp64 factorisation stage, every kernel that computes
+    the build's SVDs and centre moves (Jacobi Gram and rotation passes, the
+    Gram/Cholesky preconditioner, CholeskyQR, projections, Newton-Schulz):
+    algorithmic work = the nominal flops of those factorisations (thin SVD
+    4 (14 m n^2 + 8 n^3) per update, Householder QR 4 (2 m n^2 - 2 n^3 / 3)
+    per centre move); time = each class's probed average launch time, less
+    the event floor, times its launches."""
     by = {p["name"]: p for p in prof}
     t_total, launches, detail = 0.0, 0, {}
-    for name in ("k_jac_gram", "k_jac_rotate"):
+    for name in ("k_jac_gram", "k_jac_rotate", "k_factor_other"):
         p = by[name]
         if not p["timed"]:
             continue
@@ -242,7 +243,7 @@ def svd_roofline(prof, inf, floor_s, steps):
     achieved = work / t_total if t_total > 0 else 0.0
     return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAKS["fp64"], "traffic": None,
-            "kernel": "k_jac_gram + k_jac_rotate (fp64 SVDs and centre moves)",
+            "kernel": "k_jac_rotate + k_jac_gram + k_factor_other (fp64 SVDs and centre moves)",
             "kernel_source_sha": source_hash("k_jac_rotate"), "dtype": "fp64",
             "work_per_step_flop": inf.nominal_svd_flops + inf.nominal_qr_flops,
             "nominal_svd_flop": inf.nominal_svd_flops, "nominal_qr_flop": inf.nominal_qr_flops,

@@ -235,8 +235,7 @@ typedef struct {
   int32_t n_center_moves;  /* single-site orthogonalisations (centre moves) */
   double nominal_svd_flops;/* sum over full SVDs of 4 (14 m n^2 + 8 n^3),    */
                            /* m >= n the two-site matrix shape              */
-  double nominal_qr_flops; /* sum over the centre moves done by the Jacobi */
-                           /* orthogonalisation of 4 (2 m n^2 - 2n^3/3)     */
+  double nominal_qr_flops; /* sum over centre moves of 4 (2 m n^2 - 2n^3/3) */
   int32_t n_precond;       /* full SVDs done on the Cholesky-preconditioned */
                            /* matrix (Jacobi on R^H, R^H R = X^H X)         */
   int32_t n_precond_fallback; /* preconditioned attempts redone on X itself */
@@ -410,7 +409,11 @@ rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float
  * together with the algorithmic flops and HBM bytes of that launch;
  * every = 0 disables probing.  Both calls clear the counters.  Classes:
  * 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram, 2 Jacobi rotation,
- * 3 two-site contraction, 4 randomized range finder. */
+ * 3 two-site contraction, 4 randomized range finder, 5 the other fp64
+ * factorisation kernels (Gram and Cholesky preconditioner, CholeskyQR,
+ * triangular inverse, projections, Newton-Schulz, ranks); class 5 times
+ * every launch (its kernels differ in size, so a fixed stride could alias
+ * with their launch pattern) and records no flops or bytes. */
 rcs_status rcs_profile_enable(int32_t every);
 /* Median event interval (seconds, host output) of back-to-back launches of
  * an empty one-workgroup kernel on the null stream, timed the same way: the

@@ -135,7 +135,8 @@ _lib.rcs_build_opts_default.restype = None
 EXPORTED = sorted(list(_SIGS) + ["rcs_last_error", "rcs_version", "rcs_circuit_destroy",
                                  "rcs_state_destroy", "rcs_build_opts_default",
                                  "rcs_profile_class_name", "rcs_tuning_clear"])
-KERNEL_CLASSES = ["k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder"]
+KERNEL_CLASSES = ["k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder",
+                  "k_factor_other"]
 
 
 def _check(st):

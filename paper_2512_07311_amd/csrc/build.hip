@@ -659,9 +659,9 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   RCS_REQUIRE(pl.cnt <= SORT_MAX, "matrix too wide for the rank kernel");
   double2* X = ws.X.as<double2>();
   // ||X||_F^2 scales the Jacobi's numerically-zero column threshold
-  hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
+  RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), pl.cnt,
+  RCS_PROBED_LAUNCH(kKcFactor, k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), pl.cnt,
                      reinterpret_cast<double*>(ws.host_rank_dev()));
   HIP_LAUNCH_OK();
   HIP_OK(hipMemcpyAsync(&ws.host_rank->w, ws.host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
@@ -669,18 +669,18 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   const double fro2 = ws.host_rank->w;
   if (sort_columns_first()) {
     // order columns by norm (X0 keeps the original order for the projection)
-    hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, pl.cnt, 0.0,
+    RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, pl.cnt, 0.0,
                        ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
     HIP_LAUNCH_OK();
-    hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(pl.len, 256), pl.cnt), dim3(256), 0, s, ws.X0.as<double2>(),
+    RCS_PROBED_LAUNCH(kKcFactor, k_permute_cols, dim3(ceil_div(pl.len, 256), pl.cnt), dim3(256), 0, s, ws.X0.as<double2>(),
                        pl.ldx, pl.len, ws.order.as<int>(), X);
     HIP_LAUNCH_OK();
   }
   int sweeps = jacobi_run(pl, X, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60, ortho_only ? 1e-7 : 0.0);
   st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
-  hipLaunchKernelGGL(k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
+  RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(pl.cnt), dim3(256), 0, s, X, pl.ldx, pl.len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, cap, eps,
+  RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), pl.cnt, cap, eps,
                      ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), extra_dev);
   HIP_LAUNCH_OK();
   HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
@@ -694,7 +694,7 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
                           hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
   }
-  hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(pl.ldx, 256), out.k), dim3(256), 0, s, X, pl.ldx,
+  RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize, dim3(ceil_div(pl.ldx, 256), out.k), dim3(256), 0, s, X, pl.ldx,
                      ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
   HIP_LAUNCH_OK();
   // orthonormalise: X <- Wn (3I - Wn^H Wn)/2 (X is free after the gather);
@@ -702,17 +702,17 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
   double2* src = ws.Wn.as<double2>();
   double2* dst = X;
   for (int it = 0; it < (ortho_only ? 2 : 1); ++it) {
-    hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(out.k, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s, src,
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(out.k, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s, src,
                        pl.ldx, pl.len, out.k, ws.H.as<double2>());
     HIP_LAUNCH_OK();
-    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(out.k, GT_N), ceil_div(pl.len, GT_M)), dim3(GT_THREADS), 0, s,
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_apply, dim3(ceil_div(out.k, GT_N), ceil_div(pl.len, GT_M)), dim3(GT_THREADS), 0, s,
                        src, pl.ldx, pl.len, out.k, ws.H.as<double2>(), dst);
     HIP_LAUNCH_OK();
     std::swap(src, dst);
   }
   ws.wn_final = src;
   const double scale = renorm ? 1.0 / out.nrm : 1.0;
-  hipLaunchKernelGGL(k_project, dim3(ceil_div(pl.cnt, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
+  RCS_PROBED_LAUNCH(kKcFactor, k_project, dim3(ceil_div(pl.cnt, GT_N), ceil_div(out.k, GT_M)), dim3(GT_THREADS), 0, s,
                      ws.wn_final, ws.X0.as<double2>(), pl.ldx, pl.len, out.k, pl.cnt, scale,
                      ws.P.as<double2>());
   HIP_LAUNCH_OK();
@@ -746,17 +746,17 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   RCS_REQUIRE(n <= SORT_MAX, "matrix too wide for the rank kernel");
   double2* X = ws.X.as<double2>();
   double2* X0 = ws.X0.as<double2>();
-  hipLaunchKernelGGL(k_colnorm, dim3(n), dim3(256), 0, s, X0, pl.ldx, len, ws.sigma.as<double>());
+  RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(n), dim3(256), 0, s, X0, pl.ldx, len, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), n,
+  RCS_PROBED_LAUNCH(kKcFactor, k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), n,
                      reinterpret_cast<double*>(ws.host_rank_dev()));
   HIP_LAUNCH_OK();
   // columns in descending-norm order (the pivoting of the QR preconditioner)
   ws.order_x.ensure((size_t)n * sizeof(int));
-  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, n, 0.0,
+  RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, n, 0.0,
                      ws.sorted.as<double>(), ws.order_x.as<int>(), ws.scal.as<RankOut>(), nullptr);
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(len, 256), n), dim3(256), 0, s, X0, pl.ldx, len,
+  RCS_PROBED_LAUNCH(kKcFactor, k_permute_cols, dim3(ceil_div(len, 256), n), dim3(256), 0, s, X0, pl.ldx, len,
                      ws.order_x.as<int>(), X);
   HIP_LAUNCH_OK();
   const int ldg = (int)round_up(n, 64);
@@ -777,9 +777,9 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   double2* Y = ws.Y.as<double2>();
   const int sweeps = jacobi_run(py, Y, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
   st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
-  hipLaunchKernelGGL(k_colnorm, dim3(n), dim3(256), 0, s, Y, py.ldx, n, ws.sigma.as<double>());
+  RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(n), dim3(256), 0, s, Y, py.ldx, n, ws.sigma.as<double>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, cap, eps,
+  RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, cap, eps,
                      ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
   HIP_LAUNCH_OK();
   ws.host_sorted.resize(n);
@@ -803,13 +803,13 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   // kept columns of Y J, normalised: V_k in the sorted basis; one
   // Newton-Schulz step (into Y, free after the gather) makes them
   // orthonormal to rounding
-  hipLaunchKernelGGL(k_gather_normalize, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y, py.ldx,
+  RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y, py.ldx,
                      ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
+  RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
                      ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>());
   HIP_LAUNCH_OK();
-  hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(k, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s,
+  RCS_PROBED_LAUNCH(kKcFactor, k_ns_apply, dim3(ceil_div(k, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s,
                      ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>(), Y);
   HIP_LAUNCH_OK();
   // P = (X_sorted V_k)^H / nrm, and V_k back in X's column order
@@ -881,7 +881,7 @@ static bool move_cholqr(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl) {
   double2* src = Wn;
   double2* dst = X;
   for (int it = 0; it < 3; ++it) {
-    hipLaunchKernelGGL(k_ns_gram, dim3(ceil_div(n, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s, src, pl.ldx,
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(n, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s, src, pl.ldx,
                        len, n, ws.H.as<double2>());
     HIP_LAUNCH_OK();
     if (it == 0) {
@@ -893,7 +893,7 @@ static bool move_cholqr(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl) {
       dev = ws.host_rank->w;      // max |H - I| = max |I - Q^H Q| / 2
       if (*ws.host_rot != 0 || !(dev <= 0.5e-4)) return false;
     }
-    hipLaunchKernelGGL(k_ns_apply, dim3(ceil_div(n, GT_N), ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, src,
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_apply, dim3(ceil_div(n, GT_N), ceil_div(len, GT_M)), dim3(GT_THREADS), 0, s, src,
                        pl.ldx, len, n, ws.H.as<double2>(), dst);
     HIP_LAUNCH_OK();
     std::swap(src, dst);
@@ -923,7 +923,7 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
   if (cholqr_moves_enabled() && cnt >= 64 && cnt <= len && move_cholqr(st, ws, pl)) {
     k = cnt;
     st.n_moves_cholqr += 1;
-    hipLaunchKernelGGL(k_project, dim3(ceil_div(cnt, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
+    RCS_PROBED_LAUNCH(kKcFactor, k_project, dim3(ceil_div(cnt, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
                        ws.wn_final, ws.X0.as<double2>(), pl.ldx, len, k, cnt, 1.0, ws.P.as<double2>());
     HIP_LAUNCH_OK();
   } else {
@@ -932,10 +932,9 @@ static void move_center(rcs_state_s& st, BuildWork& ws, bool right) {
     HIP_OK(hipMemcpyAsync(ws.X.p, ws.X0.p, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), hipMemcpyDeviceToDevice, s));
     SplitResult r = svd_split(st, ws, pl, right ? st.cap[c + 1] : st.cap[c], 0.0, false, nullptr, nullptr, true);
     k = r.k;
-    // nominal work of the moves the Jacobi kernels do
-    st.nominal_qr_flops += nominal_qr_flops(len, cnt);
   }
   st.n_moves += 1;
+  st.nominal_qr_flops += nominal_qr_flops(len, cnt);
   hipLaunchKernelGGL(k_write_ortho, dim3(grid1d((int64_t)2 * k * std::max(dl, dr))), dim3(256), 0, s,
                      ws.wn_final, pl.ldx, k, dl, dr, right ? 1 : 0, st.site[c]);
   HIP_LAUNCH_OK();

@@ -26,6 +26,7 @@
 // identity diagonal so that the padded matrix factors as blockdiag(R, I).
 #include "chol.h"
 #include "gemm_f64.h"
+#include "prof.h"
 
 namespace rcs {
 
@@ -200,14 +201,14 @@ static void gram_cholesky(const double2* X, int ldx, int len, int n, double2* G,
                           int* flag_dev, hipStream_t s) {
   RCS_REQUIRE(ldg % CB == 0 && ldg >= n, "Gram leading dimension must be a multiple of 64");
   const int nb = ldg / CB;
-  hipLaunchKernelGGL(k_gram_upper, dim3(nb, nb), dim3(GT_THREADS), 0, s, X, ldx, len, n, G, ldg);
+  RCS_PROBED_LAUNCH(kKcFactor, k_gram_upper, dim3(nb, nb), dim3(GT_THREADS), 0, s, X, ldx, len, n, G, ldg);
   HIP_LAUNCH_OK();
   for (int jb = 0; jb < nb; ++jb) {
-    hipLaunchKernelGGL(k_chol_panel, dim3(nb - jb), dim3(PANEL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd, Ri);
+    RCS_PROBED_LAUNCH(kKcFactor, k_chol_panel, dim3(nb - jb), dim3(PANEL_THREADS), 0, s, G, ldg, jb, flag_dev, Rd, Ri);
     HIP_LAUNCH_OK();
     const int T = nb - jb - 1;
     if (T > 0) {
-      hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(GT_THREADS), 0, s, G, ldg, nb, jb);
+      RCS_PROBED_LAUNCH(kKcFactor, k_chol_update, dim3(T * (T + 1) / 2), dim3(GT_THREADS), 0, s, G, ldg, nb, jb);
       HIP_LAUNCH_OK();
     }
   }
@@ -217,7 +218,7 @@ void chol_precondition(const double2* X, int ldx, int len, int n, double2* G, in
                        int ldy, int ycols, int* flag_dev, hipStream_t s) {
   gram_cholesky(X, ldx, len, n, G, ldg, Rd, nullptr, flag_dev, s);
   const int64_t tot = (int64_t)ldy * ycols;
-  hipLaunchKernelGGL(k_chol_to_y, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65535)), dim3(256), 0, s, G,
+  RCS_PROBED_LAUNCH(kKcFactor, k_chol_to_y, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65535)), dim3(256), 0, s, G,
                      ldg, Rd, n, Y, ldy, ycols);
   HIP_LAUNCH_OK();
 }
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_cgemm_cm(const double2* A, int l
 static void cgemm_cm(const double2* A, int lda, int64_t sa, const double2* B, int ldb, int64_t sb, double2* D,
                      int ldd, int64_t sd, int M, int N, int K, double alpha, int batch, hipStream_t s) {
   if (batch <= 0 || M <= 0 || N <= 0) return;
-  hipLaunchKernelGGL(k_cgemm_cm, dim3(ceil_div(N, GT_N), ceil_div(M, GT_M), batch), dim3(GT_THREADS), 0, s, A, lda,
+  RCS_PROBED_LAUNCH(kKcFactor, k_cgemm_cm, dim3(ceil_div(N, GT_N), ceil_div(M, GT_M), batch), dim3(GT_THREADS), 0, s, A, lda,
                      sa, B, ldb, sb, D, ldd, sd, M, N, K, alpha);
   HIP_LAUNCH_OK();
 }
@@ -315,7 +316,7 @@ void max_dev_identity(const double2* H, int k, double* dev, hipStream_t s) {
   HIP_OK(hipMemsetAsync(dev, 0, sizeof(double), s));
   const int64_t tot = (int64_t)k * k;
   const int blocks = (int)std::min<int64_t>(1024, (tot + 255) / 256);
-  hipLaunchKernelGGL(k_max_dev_identity, dim3(std::max(blocks, 1)), dim3(256), 0, s, H, k, dev);
+  RCS_PROBED_LAUNCH(kKcFactor, k_max_dev_identity, dim3(std::max(blocks, 1)), dim3(256), 0, s, H, k, dev);
   HIP_LAUNCH_OK();
 }
 
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_project_rows(const double2* U, i
 
 void project_rows(const double2* U, int ldu, const double2* X, int ldx, int len, int n, int k, double scale,
                   double2* P, hipStream_t s) {
-  hipLaunchKernelGGL(k_project_rows, dim3(ceil_div(len, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s, U, ldu,
+  RCS_PROBED_LAUNCH(kKcFactor, k_project_rows, dim3(ceil_div(len, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s, U, ldu,
                      X, ldx, len, n, k, scale, P);
   HIP_LAUNCH_OK();
 }
@@ -360,7 +361,7 @@ __global__ void k_unpermute_rows(const double2* in, int ld, int n, int k, const 
 }
 
 void unpermute_rows(const double2* in, int ld, int n, int k, const int* order, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_unpermute_rows, dim3(ceil_div(n, 256), k), dim3(256), 0, s, in, ld, n, k, order, out);
+  RCS_PROBED_LAUNCH(kKcFactor, k_unpermute_rows, dim3(ceil_div(n, 256), k), dim3(256), 0, s, in, ld, n, k, order, out);
   HIP_LAUNCH_OK();
 }
 

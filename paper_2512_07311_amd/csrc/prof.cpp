@@ -73,7 +73,8 @@ Probe::Probe(int kclass, hipStream_t s, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_every <= 0) return;
   g_tot[kclass].launches += 1;
-  if ((g_counter[kclass]++ % g_every) != 0) return;
+  const int every = kclass == kKcFactor ? 1 : g_every;
+  if ((g_counter[kclass]++ % every) != 0) return;
   if (g_pending.size() > 4096) drain(false);
   g_pending.push_back(Pending{get_event(), get_event(), kclass, flops, bytes, false});
   Pending* p = &g_pending.back();
@@ -159,7 +160,8 @@ rcs_status rcs_profile_event_floor(double* seconds) {
 }
 
 const char* rcs_profile_class_name(int32_t kclass) {
-  static const char* names[] = {"k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder"};
+  static const char* names[] = {"k_chain_gemm", "k_jac_gram", "k_jac_rotate", "k_two_site", "k_range_finder",
+                                "k_factor_other"};
   return (kclass >= 0 && kclass < rcs::kKcCount) ? names[kclass] : "";
 }
 

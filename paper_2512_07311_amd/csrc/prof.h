@@ -16,8 +16,18 @@ enum KernelClass : int {
   kKcJacRotate = 2,   // Jacobi inner solve + block rotation
   kKcTwoSite = 3,     // two-site contraction
   kKcRange = 4,       // randomized range-finder products (fp32)
-  kKcCount = 5
+  kKcFactor = 5,      // the other fp64 factorisation kernels (Gram, Cholesky,
+                      // triangular inverse, projections, Newton-Schulz, ranks);
+                      // every launch is timed, the kernels differ in size
+  kKcCount = 6
 };
+
+// Launch `kernel` (plain arguments) timed under kernel class kc.
+#define RCS_PROBED_LAUNCH(kc, kernel, grid, block, shmem, stream, ...)                                   \
+  do {                                                                                                  \
+    ::rcs::Probe pr_(kc, stream, 0.0, 0.0);                                                             \
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, pr_.start(), pr_.stop(), 0, __VA_ARGS__); \
+  } while (0)
 
 // RAII probe: construct before the launch, pass start()/stop() to
 // hipExtLaunchKernelGGL (null when this launch is not sampled), destroy
