@@ -66,40 +66,56 @@ __device__ inline double2 cmul_hc(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// Panel jb, one wavefront per workgroup, lane c owning column c of the
-// 64 x 64 blocks in LDS:
-//  * every workgroup factors the diagonal block G_jj = R^H R (right-looking;
-//    at step k every lane reads the pivot, lanes c > k scale R[k][c] and then
-//    update their column's entries T[r][c], k < r <= c, with the broadcast
-//    row k); a pivot that is not positive and finite sets *flag;
+// Panel jb, 256 threads per workgroup: thread (q, c) = (t / 64, t % 64)
+// works on column c of the 64 x 64 blocks in LDS and on the rows (or sum
+// terms) congruent to q mod 4, so the four waves share each step's work:
+//  * every workgroup factors the diagonal block G_jj = R^H R (right-looking:
+//    at step k row k of R is formed once in a separate buffer, then each
+//    thread updates its rows of its column's trailing part); a pivot that is
+//    not positive and finite sets *flag;
 //  * workgroup 0 stores R_jj (column-major in Rd) and, when Ri is given, the
-//    diagonal block of R^{-1} (lane c back-substitutes column c of R^{-1});
+//    diagonal block of R^{-1} (back substitution on every column at once);
 //  * workgroup t >= 1 solves its tile of the block row, R_jt = R^{-H} G_jt,
-//    by forward substitution, lane c on column c.
-constexpr int PANEL_THREADS = 64;
+//    by forward substitution on every column at once.
+// The substitutions sum their terms in four interleaved partial sums,
+// combined in a fixed order.
+constexpr int PANEL_THREADS = 256;
+
+// B[r][cc] = G[row0 + r][col0 + cc] (G column-major, ld ldg) for a 64 x 64
+// block: each thread loads four columns' entries of one row, sixteen loads
+// in flight before their LDS stores.
+__device__ inline void load_block64(const double2* G, int ldg, int row0, int col0, double2 (*B)[CB + 1]) {
+  const int r = threadIdx.x & (CB - 1), q = threadIdx.x >> 6;
+  double2 v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = G[(int64_t)(col0 + q + 4 * u) * ldg + row0 + r];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) B[r][q + 4 * u] = v[u];
+}
 
 __global__ __launch_bounds__(PANEL_THREADS) void k_chol_panel(double2* G, int ldg, int jb, int* flag, double2* Rd,
                                                               double2* Ri) {
   __shared__ double2 T[CB][CB + 1];
   __shared__ double2 A[CB][CB + 1];
-  const int c = threadIdx.x;
+  __shared__ double2 rowk[CB];
+  __shared__ double2 part[4][CB];
+  const int c = threadIdx.x & (CB - 1), q = threadIdx.x >> 6;
   const int j0 = jb * CB;
-  for (int cc = 0; cc < CB; ++cc) T[c][cc] = G[(int64_t)(j0 + cc) * ldg + j0 + c];
+  load_block64(G, ldg, j0, j0, T);
   __syncthreads();
   for (int k = 0; k < CB; ++k) {
     double d = T[k][k].x;
     const bool bad = !(d > 0.0) || !(d < 1e300);
     if (bad) d = 1.0;
-    if (bad && c == 0) atomicExch(flag, 1);
+    if (bad && threadIdx.x == 0) atomicExch(flag, 1);
     const double r = sqrt(d), inv = 1.0 / r;
-    __syncthreads();                      // the pivot is read before it is overwritten
-    if (c == k) T[k][k] = make_double2(r, 0.0);
-    if (c > k) T[k][c] = make_double2(T[k][c].x * inv, T[k][c].y * inv);
+    if (q == 0 && c >= k) rowk[c] = c == k ? make_double2(r, 0.0) : make_double2(T[k][c].x * inv, T[k][c].y * inv);
     __syncthreads();
+    if (q == 0 && c >= k) T[k][c] = rowk[c];
     if (c > k) {
-      const double2 rc = T[k][c];
-      for (int rr = k + 1; rr <= c; ++rr) {
-        const double2 p = cmul_hc(T[k][rr], rc);
+      const double2 rc = rowk[c];
+      for (int rr = k + 1 + q; rr <= c; rr += 4) {
+        const double2 p = cmul_hc(rowk[rr], rc);
         T[rr][c] = make_double2(T[rr][c].x - p.x, T[rr][c].y - p.y);
       }
     }
@@ -107,44 +123,56 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_chol_panel(double2* G, int ld
   }
   if (blockIdx.x == 0) {
     double2* rd = Rd + (int64_t)jb * CB * CB;
-    for (int cc = 0; cc < CB; ++cc) rd[cc * CB + c] = c <= cc ? T[c][cc] : make_double2(0.0, 0.0);
+    for (int cc = q; cc < CB; cc += 4) rd[cc * CB + c] = c <= cc ? T[c][cc] : make_double2(0.0, 0.0);
     if (Ri) {
       // column c of R^{-1}: x_c = 1 / R_cc; x_i = -(sum_{m=i+1}^{c} R_im x_m) / R_ii, i < c
-      A[c][c] = make_double2(1.0 / T[c][c].x, 0.0);
-      for (int i = CB - 2; i >= 0; --i) {
-        if (c > i) {
-          double2 sum = make_double2(0.0, 0.0);
-          for (int m = i + 1; m <= c; ++m) {
-            const double2 p = cmul_c(T[i][m], A[m][c]);
-            sum.x += p.x;
-            sum.y += p.y;
-          }
-          const double q = -1.0 / T[i][i].x;
-          A[i][c] = make_double2(q * sum.x, q * sum.y);
-        }
-      }
+      if (q == 0) A[c][c] = make_double2(1.0 / T[c][c].x, 0.0);
       __syncthreads();
-      for (int cc = 0; cc < CB; ++cc)
+      for (int i = CB - 2; i >= 0; --i) {
+        double2 s2 = make_double2(0.0, 0.0);
+        if (c > i)
+          for (int m = i + 1 + q; m <= c; m += 4) {
+            const double2 p = cmul_c(T[i][m], A[m][c]);
+            s2.x += p.x;
+            s2.y += p.y;
+          }
+        part[q][c] = s2;
+        __syncthreads();
+        if (q == 0 && c > i) {
+          const double2 t0 = part[0][c], t1 = part[1][c], t2 = part[2][c], t3 = part[3][c];
+          const double sx = (t0.x + t1.x) + (t2.x + t3.x), sy = (t0.y + t1.y) + (t2.y + t3.y);
+          const double qq = -1.0 / T[i][i].x;
+          A[i][c] = make_double2(qq * sx, qq * sy);
+        }
+        __syncthreads();
+      }
+      for (int cc = q; cc < CB; cc += 4)
         Ri[(int64_t)(j0 + cc) * ldg + j0 + c] = c <= cc ? A[c][cc] : make_double2(0.0, 0.0);
     }
     return;
   }
   const int t0 = j0 + blockIdx.x * CB;    // first column of this tile
-  for (int cc = 0; cc < CB; ++cc) A[c][cc] = G[(int64_t)(t0 + cc) * ldg + j0 + c];
+  load_block64(G, ldg, j0, t0, A);
   __syncthreads();
   // R^H X = A, column c: X_i = (A_i - sum_{m<i} conj(R_mi) X_m) / R_ii
   for (int i = 0; i < CB; ++i) {
-    double2 sum = A[i][c];
-    for (int m = 0; m < i; ++m) {
+    double2 s2 = make_double2(0.0, 0.0);
+    for (int m = q; m < i; m += 4) {
       const double2 p = cmul_hc(T[m][i], A[m][c]);
-      sum.x -= p.x;
-      sum.y -= p.y;
+      s2.x += p.x;
+      s2.y += p.y;
     }
-    const double q = 1.0 / T[i][i].x;
-    A[i][c] = make_double2(q * sum.x, q * sum.y);
+    part[q][c] = s2;
+    __syncthreads();
+    if (q == 0) {
+      const double2 t0p = part[0][c], t1 = part[1][c], t2 = part[2][c], t3 = part[3][c];
+      const double sx = (t0p.x + t1.x) + (t2.x + t3.x), sy = (t0p.y + t1.y) + (t2.y + t3.y);
+      const double qq = 1.0 / T[i][i].x;
+      A[i][c] = make_double2(qq * (A[i][c].x - sx), qq * (A[i][c].y - sy));
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int cc = 0; cc < CB; ++cc) G[(int64_t)(t0 + cc) * ldg + j0 + c] = A[c][cc];
+  for (int cc = q; cc < CB; cc += 4) G[(int64_t)(t0 + cc) * ldg + j0 + c] = A[c][cc];
 }
 
 // Trailing update after panel jb: tile (ti, tj), jb < ti <= tj < nb:
