@@ -80,27 +80,40 @@ __device__ inline int f64_row(int lane, int r) { return (lane >> 4) + 4 * r; }
 
 // Generic A loader: element functor f(m, k) -> double2 for rows m of the
 // tile (absolute indices), with M x K bounds.  KFAST selects which index
-// consecutive threads walk (the operand's unit-stride dimension).
+// consecutive threads walk (the operand's unit-stride dimension).  fetch()
+// reads a stage into registers, commit() writes them to LDS, so that the
+// main loop can have the next stage's loads in flight during the current
+// stage's matrix-core work.
 template <class F, bool KFAST>
 struct LoadA {
+  static constexpr int PER = (GT_M * GT_K) / GT_THREADS;
   F f;
   int m0, M, K;
-  __device__ inline void operator()(SmemC64& s, int k0, int tid) const {
+  __device__ inline void index(int j, int tid, int& m, int& k) const {
+    const int e = tid + j * GT_THREADS;
+    if (KFAST) {
+      k = e % GT_K;
+      m = e / GT_K;
+    } else {
+      m = e % GT_M;
+      k = e / GT_M;
+    }
+  }
+  __device__ inline void fetch(double2 (&r)[PER], int k0, int tid) const {
 #pragma unroll
-    for (int j = 0; j < (GT_M * GT_K) / GT_THREADS; ++j) {
-      int e = tid + j * GT_THREADS;
+    for (int j = 0; j < PER; ++j) {
       int m, k;
-      if (KFAST) {
-        k = e % GT_K;
-        m = e / GT_K;
-      } else {
-        m = e % GT_M;
-        k = e / GT_M;
-      }
-      double2 v = make_double2(0.0, 0.0);
-      if (m0 + m < M && k0 + k < K) v = f(m0 + m, k0 + k);
-      s.ar[k][m] = v.x;
-      s.ai[k][m] = v.y;
+      index(j, tid, m, k);
+      r[j] = (m0 + m < M && k0 + k < K) ? f(m0 + m, k0 + k) : make_double2(0.0, 0.0);
+    }
+  }
+  __device__ inline void commit(SmemC64& s, const double2 (&r)[PER], int tid) const {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      int m, k;
+      index(j, tid, m, k);
+      s.ar[k][m] = r[j].x;
+      s.ai[k][m] = r[j].y;
     }
   }
 };
@@ -109,36 +122,58 @@ struct LoadA {
 // unit-stride index.
 template <class F, bool NFAST>
 struct LoadB {
+  static constexpr int PER = (GT_N * GT_K) / GT_THREADS;
   F f;
   int n0, K, N;
-  __device__ inline void operator()(SmemC64& s, int k0, int tid) const {
+  __device__ inline void index(int j, int tid, int& k, int& n) const {
+    const int e = tid + j * GT_THREADS;
+    if (NFAST) {
+      n = e % GT_N;
+      k = e / GT_N;
+    } else {
+      k = e % GT_K;
+      n = e / GT_K;
+    }
+  }
+  __device__ inline void fetch(double2 (&r)[PER], int k0, int tid) const {
 #pragma unroll
-    for (int j = 0; j < (GT_N * GT_K) / GT_THREADS; ++j) {
-      int e = tid + j * GT_THREADS;
-      int n, k;
-      if (NFAST) {
-        n = e % GT_N;
-        k = e / GT_N;
-      } else {
-        k = e % GT_K;
-        n = e / GT_K;
-      }
-      double2 v = make_double2(0.0, 0.0);
-      if (k0 + k < K && n0 + n < N) v = f(k0 + k, n0 + n);
-      s.br[k][n] = v.x;
-      s.bi[k][n] = v.y;
+    for (int j = 0; j < PER; ++j) {
+      int k, n;
+      index(j, tid, k, n);
+      r[j] = (k0 + k < K && n0 + n < N) ? f(k0 + k, n0 + n) : make_double2(0.0, 0.0);
+    }
+  }
+  __device__ inline void commit(SmemC64& s, const double2 (&r)[PER], int tid) const {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      int k, n;
+      index(j, tid, k, n);
+      s.br[k][n] = r[j].x;
+      s.bi[k][n] = r[j].y;
     }
   }
 };
 
+// K loop: stage k0 goes from registers to LDS, then the loads of stage
+// k0 + 16 are issued before the matrix cores work on stage k0, so global
+// latency overlaps the MFMAs (one LDS buffer, one register stage).
 template <class LA, class LB>
 __device__ inline void cgemm_mainloop(const LA& la, const LB& lb, int K, SmemC64& s, AccC64& acc) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  double2 ra[LA::PER], rb[LB::PER];
+  if (K > 0) {
+    la.fetch(ra, 0, tid);
+    lb.fetch(rb, 0, tid);
+  }
   for (int k0 = 0; k0 < K; k0 += GT_K) {
-    la(s, k0, tid);
-    lb(s, k0, tid);
+    la.commit(s, ra, tid);
+    lb.commit(s, rb, tid);
     __syncthreads();
+    if (k0 + GT_K < K) {
+      la.fetch(ra, k0 + GT_K, tid);
+      lb.fetch(rb, k0 + GT_K, tid);
+    }
     mma_stage(s, acc, wm, wn, lane);
     __syncthreads();
   }
