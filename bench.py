@@ -186,6 +186,61 @@ def batch_step_fn(rcs, torch, wl, args):
     return specs, step
 
 
+def main_true_xeb(args, wl):
+    """True linear XEB (Section 5.1: scored against the circuit's exact
+    output probabilities) of plain and learned builds of 30-qubit circuits
+    at several depths: the exact state comes from the GPU dense state vector
+    (16 GiB), each build draws wl["shots"] shots, and each shot is scored by
+    its exact probability, next to the build's own fidelity estimate.  The
+    rank network is trained on the spectra of another seed's build.  Prints
+    one JSON line; not the headline benchmark."""
+    import numpy as np
+    import torch
+    import paper_2512_07311_amd as rcs
+    from paper_2512_07311_amd import learn
+    torch.cuda.set_device(0)
+    tc = rcs.Circuit(wl["rows"], wl["cols"], wl["cycles"], args.seed + 1, network=args.network)
+    wst = rcs.State.build(tc, 256, wl["eps"], log_spectra=True)
+    X, Y = learn.dataset(wst.spectra(), tc.n, wl["cycles"], torch)
+    mlp_w, _ = learn.train(X, Y, torch, steps=1500, batch=256, seed=args.seed)
+    del wst
+    log("rank network trained on %d spectra" % X.shape[0])
+    shots = args.shots or wl["shots"]
+    psi = torch.zeros(1 << tc.n, dtype=torch.complex128, device="cuda")
+    bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
+    p = torch.zeros(shots, dtype=torch.float64, device="cuda")
+    forms = {"plain": dict(contraction="c128", rank_mode=0),
+             "learned": dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w)}
+    rows = []
+    for cyc in wl["score_cycles"]:
+        circ = rcs.Circuit(wl["rows"], wl["cols"], cyc, args.seed, network=args.network)
+        t0 = time.time()
+        rcs.dense_simulate(circ, psi)
+        torch.cuda.synchronize()
+        log("exact %d-qubit %d-cycle state in %.2f s" % (circ.n, cyc, time.time() - t0))
+        for chi in wl["chis"]:
+            for form, kw in forms.items():
+                st = rcs.State.build(circ, chi, wl["eps"], **kw)
+                inf = st.info()
+                st.sample(bits, seed=1003)
+                rcs.dense_gather(psi, circ.n, bits, p, probabilities=True)
+                xeb, se = rcs.xeb(circ.n, p)
+                rows.append({"cycles": cyc, "chi": chi, "form": form, "state_build_s": inf.build_seconds,
+                             "fidelity_est": float(np.exp(inf.log_fidelity_est)), "true_xeb": xeb,
+                             "true_xeb_stderr": se, "n_rsvd_accepted": inf.n_rsvd_accepted,
+                             "n_fallbacks": inf.n_fallbacks})
+                log("cycles %d chi %d %s: build %.2f s, F_est %.4f, true XEB %.4f +- %.4f"
+                    % (cyc, chi, form, inf.build_seconds, rows[-1]["fidelity_est"], xeb, se))
+                del st
+    out = {"metric": "true linear XEB (exact probabilities) of plain and learned builds",
+           "value": rows[0]["true_xeb"], "unit": "xeb", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded random circuit)",
+           "config": {"workload": args.workload, "qubits": tc.n, "score_cycles": list(wl["score_cycles"]),
+                      "eps": wl["eps"], "shots": shots, "swap_network": args.network, "circuit_seed": args.seed},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main_batch(args, wl):
     import numpy as np
     import torch
@@ -281,6 +336,8 @@ def main():
     wl = dict(inputs.WORKLOADS[args.workload])
     if "batch" in wl:
         return main_batch(args, wl)
+    if wl.get("true_xeb"):
+        return main_true_xeb(args, wl)
     shots = args.shots or wl["shots"]
     circ = rcs.Circuit(wl["rows"], wl["cols"], wl["cycles"], args.seed,
                        n_removed_random=wl["removed_random"], network=args.network)

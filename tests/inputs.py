@@ -22,6 +22,12 @@ WORKLOADS = {
     # U{8..20}, chi ~ U{64, 128, 256, 512} (batch seed 7), 50,000 shots each
     "rcs_batch64_n20to40": dict(batch=64, batch_seed=7, n_lo=20, n_hi=40, cyc_lo=8, cyc_hi=20,
                                 chis=(64, 128, 256, 512), eps=1e-8, shots=50_000, precision="c64"),
+    # 30 qubits, 5x6, 8/10/12 cycles: plain and learned builds at chi 1024
+    # and 256, 1M shots each scored by linear XEB against the exact
+    # probabilities (GPU dense state vector); the rank network is trained on
+    # a 14-cycle circuit of another seed
+    "rcs30_true_xeb": dict(rows=5, cols=6, cycles=14, score_cycles=(8, 10, 12), removed_random=0,
+                           chis=(1024, 256), eps=1e-8, shots=1_000_000, precision="split_bf16", true_xeb=True),
     # 53 qubits, 20 cycles, chi cap 2048, 2.5M shots
     "rcs53_6x9_c20_chi2048": dict(rows=6, cols=9, cycles=20, removed_random=1,
                                   chi=2048, eps=1e-8, shots=2_500_000,
