@@ -80,6 +80,40 @@ def source_hash(kernel):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+# kernels of the fp64 factorisation stage (Jacobi passes and the probed
+# factorisation class) and the sources that hold them
+STAGE_KERNELS = ("k_jac_gram", "k_jac_rotate", "k_cgemm_cm", "k_chol_panel", "k_chol_to_y", "k_chol_update",
+                 "k_colnorm", "k_gather_normalize", "k_gram_upper", "k_max_dev_identity", "k_ns_apply", "k_ns_gram",
+                 "k_permute_cols", "k_project", "k_project_rows", "k_sort_rank", "k_sum_sq", "k_unpermute_rows")
+STAGE_SOURCES = ("jacobi.hip", "chol.hip", "build.hip")
+
+
+def stage_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_07311_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_stage_traffic(workload, form):
+    """HBM bytes per step of the factorisation stage from the committed
+    rocprofv3 counter summaries (calibrated FETCH_SIZE + WRITE_SIZE over
+    every dispatch of STAGE_KERNELS in one step), or None when there are none
+    for the current sources."""
+    import glob
+    want = {"stage": "factorisation", "workload": workload, "form": form, "source_sha": stage_hash()}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("stage-traffic-json: "):
+                    d = json.loads(line[len("stage-traffic-json: "):])
+                    if all(d.get(k) == v for k, v in want.items()):
+                        return d["bytes_per_step"]
+    return None
+
+
 def measured_traffic(kernel, workload, form):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries (FETCH_SIZE and WRITE_SIZE runs of this workload, calibrated by a
@@ -274,7 +308,7 @@ def main_batch(args, wl):
     print(json.dumps(out), flush=True)
 
 
-def svd_roofline(prof, inf, floor_s, steps):
+def svd_roofline(prof, inf, floor_s, steps, workload=None, form=None):
     """Roofline of the fp64 factorisation stage, every kernel that computes
     the build's SVDs and centre moves (Jacobi Gram and rotation passes, the
     Gram/Cholesky preconditioner, CholeskyQR, projections, Newton-Schulz):
@@ -296,10 +330,12 @@ def svd_roofline(prof, inf, floor_s, steps):
         detail[name] = {"avg_launch_us": 1e6 * avg, "launches_per_step": p["launches"] // max(steps, 1)}
     work = steps * (inf.nominal_svd_flops + inf.nominal_qr_flops)
     achieved = work / t_total if t_total > 0 else 0.0
+    traffic = measured_stage_traffic(workload, form) if workload else None
     return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAKS["fp64"], "traffic": None,
+            "frac": achieved / PEAKS["fp64"], "traffic": traffic,
+            "traffic_basis": "HBM bytes per step over every factorisation-stage dispatch (calibrated counters)",
             "kernel": "k_jac_rotate + k_jac_gram + k_factor_other (fp64 SVDs and centre moves)",
-            "kernel_source_sha": source_hash("k_jac_rotate"), "dtype": "fp64",
+            "kernel_source_sha": stage_hash(), "dtype": "fp64",
             "work_per_step_flop": inf.nominal_svd_flops + inf.nominal_qr_flops,
             "nominal_svd_flop": inf.nominal_svd_flops, "nominal_qr_flop": inf.nominal_qr_flops,
             "kernel_seconds_per_step": t_total / max(steps, 1), "event_floor_us": 1e6 * floor_s,
@@ -415,7 +451,7 @@ def main():
     inf = st.info()
     upd = st.updates()
     sec = (t1 - t0) / n_steps
-    roof = svd_roofline(prof, inf, floor_s, n_steps)
+    roof = svd_roofline(prof, inf, floor_s, n_steps, args.workload, "plain" if run_plain else "learned")
     est = {p["name"]: p["seconds"] * (p["launches"] / p["timed"]) if p["timed"] else 0.0 for p in prof}
     roof["factorisation_share_of_step"] = roof["kernel_seconds_per_step"] / sec
     out = {

@@ -5,6 +5,10 @@
       (one line per dispatch and counter), multiplied by S
   python -m paper_2512_07311_amd.rocprof_summary stats DIR
       the kernel statistics table of DIR/*_kernel_stats.csv
+  python -m paper_2512_07311_amd.rocprof_summary stage DIR --kernels a,b,c
+      totals over the dispatches of the named kernels (short names): the
+      sum of every counter in DIR/*_counter_collection.csv if there is one,
+      else calls and total duration from DIR/*_kernel_stats.csv
 
 Rows are streamed, so multi-GB counter files are fine.  Output is a
 markdown table on stdout.
@@ -57,13 +61,44 @@ def stats(directory, top=12):
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
 
 
+def _base(name):
+    """Short kernel name without namespace and template arguments."""
+    return _short(name).split("<")[0].split("::")[-1]
+
+
+def stage(directory, kernels):
+    want = set(kernels)
+    cc = sorted(glob.glob(os.path.join(directory, "*_counter_collection.csv")))
+    if cc:
+        acc = collections.defaultdict(lambda: [0, 0.0])   # counter -> dispatches, sum
+        with open(cc[0], newline="") as f:
+            for r in csv.DictReader(f):
+                if _base(r["Kernel_Name"]) in want:
+                    a = acc[r["Counter_Name"]]
+                    a[0] += 1
+                    a[1] += float(r["Counter_Value"])
+        for c, (n, v) in sorted(acc.items()):
+            print("stage %s: %d dispatches, sum %.1f" % (c, n, v))
+        return
+    calls, ns = 0, 0.0
+    with open(_one(directory, "_kernel_stats.csv"), newline="") as f:
+        for r in csv.DictReader(f):
+            if _base(r["Name"]) in want:
+                calls += int(r["Calls"])
+                ns += float(r["TotalDurationNs"])
+    print("stage duration: %d dispatches, total %.4f s" % (calls, ns / 1e9))
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["counters", "stats"])
+    ap.add_argument("mode", choices=["counters", "stats", "stage"])
     ap.add_argument("directory")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--kernels", default="")
     a = ap.parse_args()
     if a.mode == "counters":
         counters(a.directory, a.scale)
+    elif a.mode == "stage":
+        stage(a.directory, [k for k in a.kernels.split(",") if k])
     else:
         stats(a.directory)
