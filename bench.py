@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--shots", type=int, default=None)
     ap.add_argument("--form", default="both", choices=["plain", "learned", "both"])
     ap.add_argument("--mlp", default=None, help=".npy packed network weights (learned form)")
+    ap.add_argument("--learned-svd", default="f32", choices=["f32", "f64"],
+                    help="precision of the learned form's full SVDs")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--network", default="interleaved", choices=["interleaved", "snake"],
                     help="MPS order and swap network of the schedule")
@@ -244,7 +246,8 @@ def main_true_xeb(args, wl):
     bits = torch.zeros(shots, dtype=torch.int64, device="cuda")
     p = torch.zeros(shots, dtype=torch.float64, device="cuda")
     forms = {"plain": dict(contraction="c128", rank_mode=0),
-             "learned": dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w)}
+             "learned": dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w,
+                             svd_precision=args.learned_svd)}
     rows = []
     for cyc in wl["score_cycles"]:
         circ = rcs.Circuit(wl["rows"], wl["cols"], cyc, args.seed, network=args.network)
@@ -423,7 +426,8 @@ def main():
         return st, t_s, x, se
 
     plain_kw = dict(contraction="c128", rank_mode=0)
-    learned_kw = dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w)
+    learned_kw = dict(contraction=wl["precision"], rank_mode=1, fallback_tau=1e-6, mlp_weights=mlp_w,
+                      svd_precision=args.learned_svd)
     main_kw = plain_kw if run_plain else learned_kw
     reserve_cpu = 0.0 if args.no_cpu_baseline else CPU_BASELINE_S + 10.0
 
@@ -492,7 +496,8 @@ def main():
                 "fest_rel_diff_vs_plain": float(np.exp(li.log_fidelity_est - inf.log_fidelity_est) - 1.0),
                 "build_speedup_vs_plain": inf.build_seconds / li.build_seconds,
                 "n_rsvd_accepted": li.n_rsvd_accepted, "n_fallbacks": li.n_fallbacks,
-                "contraction": wl["precision"]}
+                "n_svd_f32": li.n_svd_f32, "n_svd_f32_redone": li.n_svd_f32_redone,
+                "contraction": wl["precision"], "svd_precision": args.learned_svd}
             del lst
         else:
             out["learned"] = {"skipped": "wall-clock budget"}

@@ -141,10 +141,26 @@ typedef struct {
   int32_t log_spectra;     /* 1: keep every update's singular spectrum        */
   int32_t max_ops;         /* < 0: whole schedule; else stop after max_ops    */
   int32_t canonicalize;    /* 1 (default): end right-canonical, unit norm     */
+  int32_t svd_precision;   /* rcs_svd_precision of the full SVD (default F64) */
 } rcs_build_opts;
 
+/* Precision of the full SVD of a truncation step (Section 3.2, stage 1).
+ * RCS_SVD_F32: splits whose rank is set by the bond cap (the discarded
+ * weight exceeds the eps threshold by more than 1e-4 of the total) run the
+ * one-sided Jacobi of the Cholesky-preconditioned matrix in fp32; the kept
+ * right singular vectors are made orthonormal in fp64 by two Newton-Schulz
+ * steps and the other factor is the fp64 projection, so the stored state is
+ * the fp64 projection onto a subspace within fp32 accuracy of the optimal
+ * one.  Splits whose rank the eps threshold decides, or whose last kept
+ * squared singular value is below 1e-7 of the weight, are redone in fp64
+ * from the same preconditioned matrix.  In RCS_RANK_LEARNED mode a cut the
+ * network predicts to be cap-limited skips the randomized SVD (whose
+ * sketch cannot resolve the spectrum at the cap more cheaply) and goes to
+ * this split. */
+typedef enum { RCS_SVD_F64 = 0, RCS_SVD_F32 = 1 } rcs_svd_precision;
+
 /* Fills *opts with defaults: C128, FULL_SVD, tau 1e-6, p 16, q 2, null
- * stream, no logging, whole schedule, canonicalize. */
+ * stream, no logging, whole schedule, canonicalize, fp64 SVD. */
 void rcs_build_opts_default(rcs_build_opts* opts);
 
 /* Builds the MPS output state of the circuit with bond cap chi >= 1 and
@@ -241,6 +257,8 @@ typedef struct {
   int32_t n_precond_fallback; /* preconditioned attempts redone on X itself */
   int32_t n_center_moves_cholqr; /* centre moves done by CholeskyQR (the   */
                            /* others by the Jacobi orthogonalisation)       */
+  int32_t n_svd_f32;       /* splits whose Jacobi ran in fp32 (RCS_SVD_F32) */
+  int32_t n_svd_f32_redone;/* fp32 attempts redone in fp64                  */
 } rcs_state_info;
 
 rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out);
@@ -342,6 +360,16 @@ rcs_status rcs_dense_gather(const double* psi_dev, int32_t n_qubits, const uint6
  * x_dev is overwritten.  Errors: NUMERIC if not converged. */
 rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev, double* u_dev,
                           void* stream);
+
+/* The same SVD with the one-sided Jacobi in fp32 (the matrix is rounded to
+ * complex64 after the fp64 column sort; Gram blocks and rotations on the
+ * fp32 matrix cores; orthogonality tolerance 16 u32 sqrt(len)): singular
+ * values with absolute errors of a few u32 ||X||_2, s_dev and u_dev as
+ * above (u_dev columns orthonormal to about 1e-5).  x_dev is not modified.
+ * Used by RCS_SVD_F32 builds (Section 3.2, stage 1, at reduced precision).
+ * Errors: NUMERIC if not converged. */
+rcs_status rcs_svd_jacobi_f32(int32_t len, int32_t cnt, const double* x_dev, double* s_dev, double* u_dev,
+                              void* stream);
 
 /* Thin QR of a complex len x cnt matrix (cnt <= len, 64 <= cnt <= 4096),
  * column-major in x_dev, as the build's centre moves compute it

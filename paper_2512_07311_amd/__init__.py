@@ -26,6 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 RCS_PREC_C128, RCS_PREC_C64, RCS_PREC_SPLIT_BF16 = 0, 1, 2
 RCS_RANK_FULL_SVD, RCS_RANK_LEARNED, RCS_RANK_RSVD_AT_CAP = 0, 1, 2
 PRECISIONS = {"c128": 0, "c64": 1, "split_bf16": 2}
+SVD_PRECISIONS = {"f64": 0, "f32": 1}
 NETWORKS = {"snake": 0, "interleaved": 1}
 LATTICES = {"rect": 0, "rotated": 1}
 MLP_PARAMS = 66 * 128 + 128 + 128 * 128 + 128 + 128 * 32 + 32
@@ -54,7 +55,7 @@ class BuildOpts(C.Structure):
                 ("mlp_count", C.c_int64), ("rsvd_oversample", C.c_int32),
                 ("rsvd_power_iters", C.c_int32), ("rsvd_seed", C.c_uint64),
                 ("stream", C.c_void_p), ("log_spectra", C.c_int32), ("max_ops", C.c_int32),
-                ("canonicalize", C.c_int32)]
+                ("canonicalize", C.c_int32), ("svd_precision", C.c_int32)]
 
 
 class StateInfo(C.Structure):
@@ -66,7 +67,8 @@ class StateInfo(C.Structure):
                 ("svd_seconds", C.c_double), ("device_bytes", C.c_int64),
                 ("n_center_moves", C.c_int32), ("nominal_svd_flops", C.c_double),
                 ("nominal_qr_flops", C.c_double), ("n_precond", C.c_int32),
-                ("n_precond_fallback", C.c_int32), ("n_center_moves_cholqr", C.c_int32)]
+                ("n_precond_fallback", C.c_int32), ("n_center_moves_cholqr", C.c_int32),
+                ("n_svd_f32", C.c_int32), ("n_svd_f32_redone", C.c_int32)]
 
 
 _vp, _i32, _i64, _u64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -98,6 +100,7 @@ _SIGS = {
     "rcs_state_updates": [_vp, _P(_i32), _P(_i32)],
     "rcs_state_rsvd_log": [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_d), _P(C.c_float), _P(_d)],
     "rcs_svd_jacobi": [_i32, _i32, _vp, _vp, _vp, _vp],
+    "rcs_svd_jacobi_f32": [_i32, _i32, _vp, _vp, _vp, _vp],
     "rcs_dense_simulate": [_vp, _vp, _i64, _vp],
     "rcs_dense_gather": [_vp, _i32, _vp, _u64, _i32, _vp, _vp],
     "rcs_cholqr": [_i32, _i32, _vp, _vp, _vp, _vp],
@@ -204,7 +207,7 @@ class Circuit:
 # ------------------------------------------------------------------- states
 def build_opts(contraction="c128", rank_mode=RCS_RANK_FULL_SVD, fallback_tau=1e-6,
                mlp_weights=None, rsvd_oversample=16, rsvd_power_iters=2, rsvd_seed=0x5EED,
-               stream=None, log_spectra=False, max_ops=-1, canonicalize=True):
+               stream=None, log_spectra=False, max_ops=-1, canonicalize=True, svd_precision="f64"):
     o = BuildOpts()
     _lib.rcs_build_opts_default(C.byref(o))
     o.contraction = PRECISIONS[contraction] if isinstance(contraction, str) else int(contraction)
@@ -222,6 +225,7 @@ def build_opts(contraction="c128", rank_mode=RCS_RANK_FULL_SVD, fallback_tau=1e-
     o.log_spectra = 1 if log_spectra else 0
     o.max_ops = max_ops
     o.canonicalize = 1 if canonicalize else 0
+    o.svd_precision = SVD_PRECISIONS[svd_precision] if isinstance(svd_precision, str) else int(svd_precision)
     return o, keep
 
 
@@ -411,6 +415,12 @@ def svd_jacobi(x, s, u, stream=None):
     len x cnt matrix); overwritten.  s: float64 (cnt,), u: complex128 like x."""
     cnt, ln = x.shape
     _check(_lib.rcs_svd_jacobi(ln, cnt, _ptr(x), _ptr(s), _ptr(u), _stream_ptr(stream)))
+
+
+def svd_jacobi_f32(x, s, u, stream=None):
+    """As svd_jacobi with the Jacobi in fp32; x (complex128) is not modified."""
+    cnt, ln = x.shape
+    _check(_lib.rcs_svd_jacobi_f32(ln, cnt, _ptr(x), _ptr(s), _ptr(u), _stream_ptr(stream)))
 
 
 def dense_simulate(circuit, psi, stream=None):

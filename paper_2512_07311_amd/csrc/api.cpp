@@ -108,6 +108,8 @@ rcs_status rcs_state_info_get(rcs_state s, rcs_state_info* out) {
   inf.n_precond = s->n_precond;
   inf.n_precond_fallback = s->n_precond_fallback;
   inf.n_center_moves_cholqr = s->n_moves_cholqr;
+  inf.n_svd_f32 = s->n_svd_f32;
+  inf.n_svd_f32_redone = s->n_svd_f32_redone;
   *out = inf;
   RCS_API_END
 }

@@ -19,6 +19,7 @@ struct BuildOptions {
   bool log_spectra = false;
   int max_ops = -1;
   bool canonicalize = true;
+  bool svd_f32 = false;      // RCS_SVD_F32
 };
 
 struct BuildWork;

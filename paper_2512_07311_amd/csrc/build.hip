@@ -217,6 +217,33 @@ __global__ void k_colnorm(const double2* X, int ldx, int len, double* sigma) {
   if (threadIdx.x == 0) sigma[j] = sqrt(red[0]);
 }
 
+// fp32 copies of fp64 columns, and column norms of fp32 columns (fp64 sums).
+__global__ void k_to_c64(const double2* X, float2* Y, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    Y[e] = make_float2((float)X[e].x, (float)X[e].y);
+}
+__global__ void k_scale_c128(double2* x, int64_t n, double a) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = make_double2(x[e].x * a, x[e].y * a);
+}
+__global__ void k_colnorm_c64(const float2* X, int ldx, int len, double* sigma) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const float2* col = X + (int64_t)j * ldx;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < len; r += 256) {
+    const double x = col[r].x, y = col[r].y;
+    s += x * x + y * y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[j] = sqrt(red[0]);
+}
+
 // Permute columns of X (len x cnt) into Xs by descending norm (order from
 // k_sort_rank); sorted columns converge faster under cyclic Jacobi.
 __global__ void k_permute_cols(const double2* X, int ldx, int len, const int* order, double2* Xs) {
@@ -356,6 +383,18 @@ __global__ void k_gather_normalize(const double2* X, int ldx, const int* order, 
   double2* dst = Wn + (int64_t)j * ldx;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ldx; r += gridDim.x * blockDim.x) {
     double2 v = src[r];
+    dst[r] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
+__global__ void k_gather_normalize_c64(const float2* X, int ldx, const int* order, const double* sorted,
+                                       double2* Wn) {
+  const int j = blockIdx.y;
+  const double inv = 1.0 / sorted[j];
+  const float2* src = X + (int64_t)order[j] * ldx;
+  double2* dst = Wn + (int64_t)j * ldx;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ldx; r += gridDim.x * blockDim.x) {
+    const float2 v = src[r];
     dst[r] = make_double2(v.x * inv, v.y * inv);
   }
 }
@@ -554,6 +593,20 @@ __global__ void k_copy_in(const double2* x, int len, int cnt, double2* X, int ld
   }
 }
 
+// The same from fp32 columns.
+__global__ void k_copy_out_c64(const float2* X, int ldx, int len, int cnt, const int* order, const double* sorted,
+                               double* s, double2* u) {
+  const int j = blockIdx.y;
+  const double sv = sorted[j];
+  const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s[j] = sv;
+  const float2* src = X + (int64_t)order[j] * ldx;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < len; r += gridDim.x * blockDim.x) {
+    const float2 v = src[r];
+    u[(int64_t)j * len + r] = make_double2(v.x * inv, v.y * inv);
+  }
+}
+
 // s[j] = sorted[j]; u[:, j] = X[:, order[j]] / sorted[j] (0 when sorted[j] = 0)
 __global__ void k_copy_out(const double2* X, int ldx, int len, int cnt, const int* order,
                            const double* sorted, double* s, double2* u) {
@@ -609,6 +662,7 @@ __global__ void k_to_device_layout(const double2* in, int da, int db, double2* o
 struct BuildWork {
   DevBuf T, X, X0, Wn, P, H, jac, sigma, sorted, order, scal, rot, tmp;
   DevBuf G, Rd, Y, order_x, cflag;   // preconditioned split
+  DevBuf Y32;                         // its fp32 copy (RCS_SVD_F32)
   DevBuf Ri, Tq, qdev;                // CholeskyQR centre moves
   std::vector<double> host_sorted;
   double2* wn_final = nullptr;   // orthonormal kept columns after svd_split
@@ -739,8 +793,18 @@ static bool svd_precondition_enabled() {
 // singular value must exceed 1e-10 of the weight, and the discarded weight
 // must clear the eps threshold by 1e-9 of the weight on the side the rank
 // rule decided.
+//
+// f32: the Jacobi first runs on an fp32 copy of Y.  Its result is used when
+// the bond cap decides the rank by a clear margin (discarded weight above
+// the eps threshold by 1e-4 of the weight, or nothing discarded) and the
+// last kept squared singular value is at least 1e-7 of the weight: fp32
+// singular values carry absolute errors of a few u32 ||Y||, so these
+// margins keep the rank and the kept subspace those of the fp64 split up to
+// fp32 accuracy.  The kept columns then get two fp64 Newton-Schulz steps
+// (orthogonality ~1e-5 -> ~1e-10 -> rounding).  Otherwise the fp64 Jacobi
+// runs on Y, which the fp32 attempt left untouched.
 static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl, int cap, double eps, bool renorm,
-                           std::vector<double>* spectrum_out, SplitResult& out, int* ldw) {
+                           std::vector<double>* spectrum_out, SplitResult& out, int* ldw, bool f32) {
   hipStream_t s = st.stream;
   const int n = pl.cnt, len = pl.len;
   RCS_REQUIRE(n <= SORT_MAX, "matrix too wide for the rank kernel");
@@ -775,47 +839,118 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   const double fro2 = ws.host_rank->w;
   if (*ws.host_rot != 0) return false;
   double2* Y = ws.Y.as<double2>();
-  const int sweeps = jacobi_run(py, Y, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
-  st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
-  RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(n), dim3(256), 0, s, Y, py.ldx, n, ws.sigma.as<double>());
-  HIP_LAUNCH_OK();
-  RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, cap, eps,
-                     ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
-  HIP_LAUNCH_OK();
   ws.host_sorted.resize(n);
-  HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(ws.host_sorted.data(), ws.sorted.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const RankOut r = *ws.host_rank;
-  if (r.bad || r.k < 1) return false;
-  {
-    const double W = r.w;
+  // rank rule on the Jacobi's columns; fills host_rank and host_sorted
+  auto rank = [&](const void* cols, bool c64) {
+    if (c64)
+      RCS_PROBED_LAUNCH(kKcFactor, k_colnorm_c64, dim3(n), dim3(256), 0, s, static_cast<const float2*>(cols), py.ldx, n,
+                        ws.sigma.as<double>());
+    else
+      RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(n), dim3(256), 0, s, static_cast<const double2*>(cols), py.ldx, n,
+                        ws.sigma.as<double>());
+    HIP_LAUNCH_OK();
+    RCS_PROBED_LAUNCH(kKcFactor, k_sort_rank, dim3(1), dim3(1024), 0, s, ws.sigma.as<double>(), n, cap, eps,
+                       ws.sorted.as<double>(), ws.order.as<int>(), ws.scal.as<RankOut>(), nullptr);
+    HIP_LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(ws.host_rank, ws.scal.p, sizeof(RankOut), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ws.host_sorted.data(), ws.sorted.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return *ws.host_rank;
+  };
+  // discarded weight beyond the rank rule's k and the last kept squared value
+  auto tail = [&](const RankOut& r, double* sk2) {
     double tk = 0.0;
     for (int i = n - 1; i >= r.k; --i) tk += ws.host_sorted[i] * ws.host_sorted[i];
-    const double sk2 = ws.host_sorted[r.k - 1] * ws.host_sorted[r.k - 1];
+    *sk2 = ws.host_sorted[r.k - 1] * ws.host_sorted[r.k - 1];
+    return tk;
+  };
+  float2* Y32 = nullptr;
+  RankOut r{};
+  int sweeps = 0;
+  bool use32 = false;
+  if (f32) {
+    ws.Y32.ensure((size_t)py.ldx * py.cnt_pad * sizeof(float2));
+    Y32 = ws.Y32.as<float2>();
+    const int64_t ne = (int64_t)py.ldx * py.cnt_pad;
+    RCS_PROBED_LAUNCH(kKcFactor, k_to_c64, dim3(grid1d(ne)), dim3(256), 0, s, Y, Y32, ne);
+    HIP_LAUNCH_OK();
+    sweeps = jacobi_run_f32(py, Y32, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
+    r = rank(Y32, true);
+    if (!r.bad && r.k >= 1) {
+      double sk2;
+      const double tk = tail(r, &sk2), W = r.w;
+      use32 = (r.k == n || tk > eps * W + 1e-4 * W) && sk2 >= 1e-7 * W;
+    }
+    if (use32)
+      st.n_svd_f32 += 1;
+    else
+      st.n_svd_f32_redone += 1;
+  }
+  if (!use32) {
+    sweeps = jacobi_run(py, Y, ws.jac.p, ws.rot.as<int>(), ws.host_rot, fro2, s, 60);
+    r = rank(Y, false);
+    if (r.bad || r.k < 1) return false;
+    double sk2;
+    const double tk = tail(r, &sk2), W = r.w;
     const double thr = eps * W, delta = 1e-9 * W;
     const bool decided = r.k == n || tk > thr + delta || (tk <= thr - delta && tk + sk2 > thr + delta);
     if (!(sk2 >= 1e-10 * W) || !decided) return false;
   }
+  st.jacobi_sweeps_max = std::max(st.jacobi_sweeps_max, sweeps);
   out = SplitResult{r.k, r.nnz, sweeps, r.eps_step, r.w, r.nrm};
   if (spectrum_out) spectrum_out->assign(ws.host_sorted.begin(), ws.host_sorted.end());
   const int k = r.k;
-  // kept columns of Y J, normalised: V_k in the sorted basis; one
-  // Newton-Schulz step (into Y, free after the gather) makes them
-  // orthonormal to rounding
-  RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y, py.ldx,
-                     ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
+  // kept columns of Y J, normalised: V_k in the sorted basis.  Newton-Schulz
+  // steps make them orthonormal to rounding: one after the fp64 Jacobi
+  // (into Y, free after the gather), two after the fp32 one (Wn -> Y -> Wn).
+  double2* Wn = ws.Wn.as<double2>();
+  if (use32)
+    RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize_c64, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y32,
+                       py.ldx, ws.order.as<int>(), ws.sorted.as<double>(), Wn);
+  else
+    RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y, py.ldx,
+                       ws.order.as<int>(), ws.sorted.as<double>(), Wn);
   HIP_LAUNCH_OK();
-  RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s,
-                     ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>());
-  HIP_LAUNCH_OK();
-  RCS_PROBED_LAUNCH(kKcFactor, k_ns_apply, dim3(ceil_div(k, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s,
-                     ws.Wn.as<double2>(), py.ldx, n, k, ws.H.as<double2>(), Y);
-  HIP_LAUNCH_OK();
-  // P = (X_sorted V_k)^H / nrm, and V_k back in X's column order
-  project_rows(Y, py.ldx, X, pl.ldx, len, n, k, renorm ? 1.0 / r.nrm : 1.0, ws.P.as<double2>(), s);
-  unpermute_rows(Y, py.ldx, n, k, ws.order_x.as<int>(), ws.Wn.as<double2>(), s);
-  ws.wn_final = ws.Wn.as<double2>();
+  double2* src = Wn;
+  double2* dst = Y;
+  for (int it = 0; it < (use32 ? 2 : 1); ++it) {
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s, src,
+                       py.ldx, n, k, ws.H.as<double2>());
+    HIP_LAUNCH_OK();
+    RCS_PROBED_LAUNCH(kKcFactor, k_ns_apply, dim3(ceil_div(k, GT_N), ceil_div(n, GT_M)), dim3(GT_THREADS), 0, s, src,
+                       py.ldx, n, k, ws.H.as<double2>(), dst);
+    HIP_LAUNCH_OK();
+    std::swap(src, dst);
+  }
+  // P = (X_sorted V_k)^H / nrm, and V_k back in X's column order (into the
+  // other buffer)
+  if (!use32) {
+    project_rows(src, py.ldx, X, pl.ldx, len, n, k, renorm ? 1.0 / r.nrm : 1.0, ws.P.as<double2>(), s);
+  } else {
+    // the kept weight ||X V_k||_F^2 of the fp64 projection gives nrm and the
+    // discarded fraction (fp32 singular values drift by ~1e-4 of the largest)
+    double2* P = ws.P.as<double2>();
+    project_rows(src, py.ldx, X, pl.ldx, len, n, k, 1.0, P, s);
+    RCS_PROBED_LAUNCH(kKcFactor, k_colnorm, dim3(k), dim3(256), 0, s, P, len, len, ws.sigma.as<double>());
+    HIP_LAUNCH_OK();
+    RCS_PROBED_LAUNCH(kKcFactor, k_sum_sq, dim3(1), dim3(256), 0, s, ws.sigma.as<double>(), k,
+                       reinterpret_cast<double*>(ws.host_rank_dev()));
+    HIP_LAUNCH_OK();
+    double kept = 0.0;
+    HIP_OK(hipMemcpyAsync(&kept, ws.host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (!(kept > 0.0)) fail(RCS_ERR_NUMERIC, "non-finite or zero kept weight");
+    out.nrm = std::sqrt(kept);
+    out.w = fro2;
+    out.eps_step = std::max(0.0, 1.0 - kept / fro2);
+    if (renorm) {
+      const int64_t ne = (int64_t)k * len;
+      RCS_PROBED_LAUNCH(kKcFactor, k_scale_c128, dim3(grid1d(ne)), dim3(256), 0, s, P, ne, 1.0 / out.nrm);
+      HIP_LAUNCH_OK();
+    }
+  }
+  unpermute_rows(src, py.ldx, n, k, ws.order_x.as<int>(), dst, s);
+  ws.wn_final = dst;
   *ldw = py.ldx;
   return true;
 }
@@ -1038,6 +1173,8 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   rec.k_hat = k_hat;
   rec.l = l;
   if (l >= m) return false;   // the sketch would cover the whole space: plain split
+  // predicted cap-limited cut with the fp32 full SVD available: no sketch
+  if (o.svd_f32 && o.rank_mode == RCS_RANK_LEARNED && k_hat >= cap) return false;
   // M (len x cnt, column-major) from the products
   const int ldm = (int)round_up(len, 64);
   ctx.M.ensure((size_t)ldm * round_up(cnt, 64) * sizeof(double2));
@@ -1174,7 +1311,8 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
   std::vector<double> spec;
   SplitResult r{};
   int ldw = pl.ldx, p_row = pl.cnt, side = orient;
-  if (precond && svd_split_chol(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr, r, &ldw)) {
+  if (precond && svd_split_chol(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr, r, &ldw,
+                                ctx.o && ctx.o->svd_f32)) {
     // orthonormal factor on X's column side: the other orientation's layout
     side = 3 - orient;
     p_row = len;
@@ -1371,6 +1509,7 @@ void rcs_build_opts_default(rcs_build_opts* o) {
   o->rsvd_seed = 0x5eed;
   o->max_ops = -1;
   o->canonicalize = 1;
+  o->svd_precision = RCS_SVD_F64;
 }
 
 static rcs::BuildOptions to_options(const rcs_build_opts* opts) {
@@ -1380,6 +1519,7 @@ static rcs::BuildOptions to_options(const rcs_build_opts* opts) {
   rcs::BuildOptions b;
   RCS_REQUIRE(o.contraction >= 0 && o.contraction <= 2, "bad contraction precision");
   RCS_REQUIRE(o.rank_mode >= 0 && o.rank_mode <= 2, "bad rank mode");
+  RCS_REQUIRE(o.svd_precision == RCS_SVD_F64 || o.svd_precision == RCS_SVD_F32, "bad SVD precision");
   b.contraction = o.contraction;
   b.rank_mode = o.rank_mode;
   b.fallback_tau = o.fallback_tau;
@@ -1392,6 +1532,7 @@ static rcs::BuildOptions to_options(const rcs_build_opts* opts) {
   b.log_spectra = o.log_spectra != 0;
   b.max_ops = o.max_ops;
   b.canonicalize = o.canonicalize != 0;
+  b.svd_f32 = o.svd_precision == RCS_SVD_F32;
   if (b.rank_mode == RCS_RANK_LEARNED)
     RCS_REQUIRE((int64_t)b.mlp.size() == RCS_MLP_PARAMS, "learned mode needs the packed network weights");
   return b;
@@ -1456,6 +1597,55 @@ rcs_status rcs_svd_jacobi(int32_t len, int32_t cnt, double* x_dev, double* s_dev
   HIP_LAUNCH_OK();
   hipLaunchKernelGGL(rcs::k_copy_out, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s, X, pl.ldx, len, cnt,
                      ws->order.as<int>(), ws->sorted.as<double>(), s_dev, reinterpret_cast<double2*>(u_dev));
+  HIP_LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  RCS_API_END
+}
+
+rcs_status rcs_svd_jacobi_f32(int32_t len, int32_t cnt, const double* x_dev, double* s_dev, double* u_dev,
+                              void* stream) {
+  RCS_API_BEGIN
+  RCS_REQUIRE(x_dev && s_dev && u_dev, "null device pointer");
+  RCS_REQUIRE(len >= 1 && cnt >= 1 && cnt <= rcs::SORT_MAX && len <= 16384, "bad matrix shape");
+  hipStream_t s = rcs::as_stream(stream);
+  rcs::JacobiPlan pl = rcs::jacobi_plan(len, cnt);
+  std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
+  rcs::ensure_work(*ws, pl, 0);
+  HIP_OK(hipMemsetAsync(ws->X.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  HIP_OK(hipMemsetAsync(ws->X0.p, 0, (size_t)pl.ldx * pl.cnt_pad * sizeof(double2), s));
+  double2* X = ws->X.as<double2>();
+  hipLaunchKernelGGL(rcs::k_copy_in, dim3(rcs::grid1d((int64_t)len * cnt)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x_dev), len, cnt, ws->X0.as<double2>(), pl.ldx);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_colnorm, dim3(cnt), dim3(256), 0, s, ws->X0.as<double2>(), pl.ldx, len,
+                     ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  // columns in descending-norm order, then the fp32 copy
+  hipLaunchKernelGGL(rcs::k_sort_rank, dim3(1), dim3(1024), 0, s, ws->sigma.as<double>(), cnt, cnt, 0.0,
+                     ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_permute_cols, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s,
+                     ws->X0.as<double2>(), pl.ldx, len, ws->order.as<int>(), X);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sum_sq, dim3(1), dim3(256), 0, s, ws->sigma.as<double>(), cnt,
+                     reinterpret_cast<double*>(ws->host_rank_dev()));
+  HIP_LAUNCH_OK();
+  const int64_t ne = (int64_t)pl.ldx * pl.cnt_pad;
+  ws->Y32.ensure((size_t)ne * sizeof(float2));
+  float2* X32 = ws->Y32.as<float2>();
+  hipLaunchKernelGGL(rcs::k_to_c64, dim3(rcs::grid1d(ne)), dim3(256), 0, s, X, X32, ne);
+  HIP_LAUNCH_OK();
+  double fro2 = 0.0;
+  HIP_OK(hipMemcpyAsync(&fro2, ws->host_rank_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  rcs::jacobi_run_f32(pl, X32, ws->jac.p, ws->rot.as<int>(), ws->host_rot, fro2, s, 60);
+  hipLaunchKernelGGL(rcs::k_colnorm_c64, dim3(cnt), dim3(256), 0, s, X32, pl.ldx, len, ws->sigma.as<double>());
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_sort_rank, dim3(1), dim3(1024), 0, s, ws->sigma.as<double>(), cnt, cnt, 0.0,
+                     ws->sorted.as<double>(), ws->order.as<int>(), ws->scal.as<rcs::RankOut>(), nullptr);
+  HIP_LAUNCH_OK();
+  hipLaunchKernelGGL(rcs::k_copy_out_c64, dim3(rcs::ceil_div(len, 256), cnt), dim3(256), 0, s, X32, pl.ldx, len,
+                     cnt, ws->order.as<int>(), ws->sorted.as<double>(), s_dev, reinterpret_cast<double2*>(u_dev));
   HIP_LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
   RCS_API_END

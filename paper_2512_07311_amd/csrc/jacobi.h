@@ -1,4 +1,4 @@
-// Internal interface of the fp64 one-sided block Jacobi SVD.
+// Internal interface of the one-sided block Jacobi SVD (fp64 and fp32).
 #pragma once
 
 #include "common.h"
@@ -27,5 +27,9 @@ void jacobi_init_attributes();
 // tol > 0 replaces the default relative orthogonality tolerance 16 u sqrt(len).
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
                int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol = 0.0);
+// The same in fp32 (complex64 columns, u = 2^-24); work as sized by
+// jacobi_work_bytes.
+int jacobi_run_f32(const JacobiPlan& pl, float2* x, void* work, int* rot_count_dev,
+                   int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol = 0.0);
 
 }  // namespace rcs

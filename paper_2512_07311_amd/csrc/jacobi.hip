@@ -1,5 +1,7 @@
-// One-sided block Jacobi SVD in fp64 (Hestenes method, block variant with a
-// Gram-matrix inner eigensolver).
+// One-sided block Jacobi SVD (Hestenes method, block variant with a
+// Gram-matrix inner eigensolver), in fp64 or fp32 (complex128 / complex64
+// data, the matching matrix-core products; R below is the real type and u
+// its unit roundoff).
 //
 // X (len x cnt, complex, column-major, leading dimension ldx, zero padded to
 // nbp*16 columns) is rotated from the right by unitary 32x32 block rotations
@@ -7,12 +9,12 @@
 // tol = 16 u sqrt(len) (fresh Grams keep relative accuracy; the margin over
 // the rounding noise of a length-len inner product keeps noise from
 // re-triggering rotations among millions of pairs), ignoring columns
-// below the fp64 noise level delta ||X||_F; the columns are then
+// below the noise level delta ||X||_F; the columns are then
 // sigma_j u_j.  Per sweep the nbp column blocks (16 columns each) meet
 // pairwise in round-robin order: nbp-1 rounds of nbp/2 disjoint pairs.  A
 // round is two launches:
 //   gram   : G_p = Y_p^H Y_p, Y_p = [X_bi | X_bj], as partial Grams over row
-//            chunks (fp64 MFMA; waves reduce in fixed order);
+//            chunks (MFMA in R; waves reduce in fixed order);
 //   rotate : every (pair, chunk) workgroup sums the partial Grams in fixed
 //            order, diagonalises the 32x32 Hermitian G_p in LDS by cyclic
 //            two-sided Jacobi (all workgroups of a pair compute the same
@@ -24,6 +26,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "gemm_f64.h"
@@ -34,30 +37,53 @@ namespace rcs {
 
 constexpr int TR = 16;        // rows per wave tile (four 4-row MFMA k steps)
 
+// Per-precision pieces: the complex type, the 16x16x4 matrix-core product
+// and the row of accumulator element r in a lane (the fp64 instruction
+// interleaves rows, the fp32 one gives each 16-lane group four consecutive
+// rows).
+template <typename R>
+struct JT;
+template <>
+struct JT<double> {
+  using C = double2;
+  using V4 = double4_t;
+  static constexpr double u = 1.11e-16;
+  static constexpr double tiny = 1e-300;
+  __device__ static V4 mma(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int orow(int lane, int r) { return (lane >> 4) + 4 * r; }
+  __host__ __device__ static C mk(double x, double y) { return make_double2(x, y); }
+};
+template <>
+struct JT<float> {
+  using C = float2;
+  using V4 = float4_t;
+  static constexpr double u = 5.97e-8;
+  static constexpr float tiny = 1e-36f;
+  __device__ static V4 mma(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
+  __host__ __device__ static C mk(float x, float y) { return make_float2(x, y); }
+};
+
 __device__ inline int rr_block(int slot, int round, int nbp) {
   return slot == 0 ? 0 : ((slot - 1 + round) % (nbp - 1)) + 1;
 }
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
-
+template <typename R>
 struct JacArgs {
-  double2* x;
+  typename JT<R>::C* x;
   int ldx, len, nbp, round, rows_per_chunk, n_chunks;   // rotate chunks
   int rows_per_gchunk, n_gchunks;                      // Gram chunks
-  double2* part;      // [pair][chunk][JP][JP]
+  typename JT<R>::C* part;   // [pair][chunk][JP][JP]
   int* rot_prev;      // [nbp] block rotated during the previous sweep
   int* rot_cur;       // [nbp] block rotated during this sweep
   int* rot_count;
-  double tol;         // relative orthogonality tolerance
-  double neg2;        // squared column norm below which a column counts as zero
+  R tol;              // relative orthogonality tolerance
+  R neg2;             // squared column norm below which a column counts as zero
   int max_inner;      // inner two-sided sweeps per pair meeting
 };
 
-__device__ inline bool pair_skipped(const JacArgs& a, int bi, int bj) {
+template <typename R>
+__device__ inline bool pair_skipped(const JacArgs<R>& a, int bi, int bj) {
   return a.rot_prev[bi] == 0 && a.rot_prev[bj] == 0 && a.rot_cur[bi] == 0 && a.rot_cur[bj] == 0;
 }
 
@@ -69,13 +95,12 @@ __device__ inline int pair_col(int c, int bi, int bj) {
 // Lane's element of every 16-column block of Y_p at one row (zero past
 // rend).  The lane's column within a block is lane % 16, so a load
 // instruction covers 16 columns x 4 consecutive rows.
-template <int JP>
-__device__ inline void load_row(const double2* x, int ldx, int bi, int bj, int row, int rend,
-                                double2 (&v)[JP / 16], int lane) {
+template <int JP, typename C>
+__device__ inline void load_row(const C* x, int ldx, int bi, int bj, int row, int rend, C (&v)[JP / 16], int lane) {
 #pragma unroll
   for (int cb = 0; cb < JP / 16; ++cb) {
     const int col = pair_col<JP>(cb * 16 + (lane & 15), bi, bj);
-    v[cb] = row < rend ? x[(int64_t)col * ldx + row] : make_double2(0.0, 0.0);
+    v[cb] = row < rend ? x[(int64_t)col * ldx + row] : C(0, 0);
   }
 }
 
@@ -83,10 +108,13 @@ __device__ inline void load_row(const double2* x, int ldx, int bi, int bj, int r
 // and each accumulates the NB(NB+1)/2 upper 16x16 blocks of Y^H Y on the
 // matrix cores straight from registers; the four waves are then reduced in
 // the fixed order ((w3 + w2) + w1) + w0 through LDS.
-template <int JP>
-__global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
+template <int JP, typename R>
+__global__ __launch_bounds__(256) void k_jac_gram(JacArgs<R> a) {
+  using T = JT<R>;
+  using C = typename T::C;
+  using V4 = typename T::V4;
   constexpr int NB = JP / 16, NU = NB * (NB + 1) / 2;
-  __shared__ double red[NU * 8][64];
+  __shared__ R red[NU * 8][64];
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
@@ -94,13 +122,13 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
   const int rbeg = chunk * a.rows_per_gchunk;
   const int rend = min(a.len, rbeg + a.rows_per_gchunk);
   const int ntiles = (rend - rbeg + TR - 1) / TR;
-  double4_t gr[NU], gi[NU];
+  V4 gr[NU], gi[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    gr[u] = double4_t{0, 0, 0, 0};
-    gi[u] = double4_t{0, 0, 0, 0};
+    gr[u] = V4{0, 0, 0, 0};
+    gi[u] = V4{0, 0, 0, 0};
   }
-  double2 cur[4][NB], nxt[4][NB];
+  C cur[4][NB], nxt[4][NB];
   const int rsub = lane >> 4;
   if (w < ntiles) {
 #pragma unroll
@@ -120,11 +148,11 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
       for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
         for (int nb = mb; nb < NB; ++nb, ++u) {
-          const double2 ym = cur[ks][mb], yn = cur[ks][nb];
-          gr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.x, gr[u], 0, 0, 0);
-          gr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.y, yn.y, gr[u], 0, 0, 0);
-          gi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ym.x, yn.y, gi[u], 0, 0, 0);
-          gi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ym.y, yn.x, gi[u], 0, 0, 0);
+          const C ym = cur[ks][mb], yn = cur[ks][nb];
+          gr[u] = T::mma(ym.x, yn.x, gr[u]);
+          gr[u] = T::mma(ym.y, yn.y, gr[u]);
+          gi[u] = T::mma(ym.x, yn.y, gi[u]);
+          gi[u] = T::mma(-ym.y, yn.x, gi[u]);
         }
     }
 #pragma unroll
@@ -138,7 +166,7 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          double vr = gr[u][r], vi = gi[u][r];
+          R vr = gr[u][r], vi = gi[u][r];
           if (src < 3) {
             vr += red[u * 8 + r][lane];
             vi += red[u * 8 + 4 + r][lane];
@@ -150,7 +178,7 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
     __syncthreads();
   }
   if (w != 0) return;
-  double2* part = a.part + ((int64_t)p * a.n_gchunks + chunk) * JP * JP;
+  C* part = a.part + ((int64_t)p * a.n_gchunks + chunk) * JP * JP;
   int u = 0;
 #pragma unroll
   for (int mb = 0; mb < NB; ++mb)
@@ -158,11 +186,11 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacArgs a) {
     for (int nb = mb; nb < NB; ++nb, ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double vr = gr[u][r] + red[u * 8 + r][lane];
-        const double vi = gi[u][r] + red[u * 8 + 4 + r][lane];
-        const int row = mb * 16 + f64_row(lane, r), col = nb * 16 + (lane & 15);
-        part[row * JP + col] = make_double2(vr, vi);
-        if (mb != nb) part[col * JP + row] = make_double2(vr, -vi);
+        const R vr = gr[u][r] + red[u * 8 + r][lane];
+        const R vi = gi[u][r] + red[u * 8 + 4 + r][lane];
+        const int row = mb * 16 + T::orow(lane, r), col = nb * 16 + (lane & 15);
+        part[row * JP + col] = T::mk(vr, vi);
+        if (mb != nb) part[col * JP + row] = T::mk(vr, -vi);
       }
 }
 
@@ -192,15 +220,17 @@ __device__ inline double rsqrt_nr(double x) {
 // c = 1/sqrt(1 + t^2 |e|^2) refined in fp64, s = t c, which makes
 // c^2 + s^2 |e|^2 = 1 to rounding.  Branch-free: inactive pairs select the
 // identity.
+template <typename R>
 struct Rot {
-  double c, s, ex, ey;
+  R c, s, ex, ey;
 };
-__device__ inline bool rot_active(double gii, double gjj, double h2, double tol, double neg2) {
-  return gii > neg2 && gjj > neg2 && h2 > 1e-300 && h2 > tol * tol * gii * gjj;
+template <typename R>
+__device__ inline bool rot_active(R gii, R gjj, R h2, R tol, R neg2) {
+  return gii > neg2 && gjj > neg2 && h2 > JT<R>::tiny && h2 > tol * tol * gii * gjj;
 }
-__device__ inline Rot jac_rot(double gii, double gjj, double2 g, double tol, double neg2) {
+__device__ inline Rot<double> jac_rot(double gii, double gjj, double2 g, double tol, double neg2) {
   const double h2 = g.x * g.x + g.y * g.y;
-  const bool act = rot_active(gii, gjj, h2, tol, neg2);
+  const bool act = rot_active<double>(gii, gjj, h2, tol, neg2);
   const double rh = __builtin_amdgcn_rsq(fmax(h2, 1e-300));
   const double tau = (gjj - gii) * (0.5 * rh);
   const float tf = (float)fabs(tau);
@@ -209,7 +239,7 @@ __device__ inline Rot jac_rot(double gii, double gjj, double2 g, double tol, dou
   const double t = tau < 0.0 ? -(double)t32 : (double)t32;
   const double ex = g.x * rh, ey = g.y * rh;
   const double c = rsqrt_nr(fma(t * t, ex * ex + ey * ey, 1.0));
-  Rot r;
+  Rot<double> r;
   r.c = act ? c : 1.0;
   r.s = act ? t * c : 0.0;
   r.ex = act ? ex : 1.0;
@@ -217,23 +247,51 @@ __device__ inline Rot jac_rot(double gii, double gjj, double2 g, double tol, dou
   return r;
 }
 
+// fp32: the same rotation with every step in fp32; c takes one Newton step
+// on the hardware 1/sqrt estimate, so c^2 (1 + t^2 |e|^2) = 1 to fp32
+// rounding.
+__device__ inline Rot<float> jac_rot(float gii, float gjj, float2 g, float tol, float neg2) {
+  const float h2 = g.x * g.x + g.y * g.y;
+  const bool act = rot_active<float>(gii, gjj, h2, tol, neg2);
+  const float rh = __builtin_amdgcn_rsqf(fmaxf(h2, JT<float>::tiny));
+  const float tau = (gjj - gii) * (0.5f * rh);
+  const float tf = fabsf(tau);
+  const float t32 = tf > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(tf)
+                               : __builtin_amdgcn_rcpf(tf + __builtin_amdgcn_sqrtf(fmaf(tf, tf, 1.0f)));
+  const float t = tau < 0.0f ? -t32 : t32;
+  const float ex = g.x * rh, ey = g.y * rh;
+  const float x = fmaf(t * t, ex * ex + ey * ey, 1.0f);
+  float c = __builtin_amdgcn_rsqf(x);
+  c = fmaf(c, fmaf(-0.5f * x * c, c, 0.5f), c);
+  Rot<float> r;
+  r.c = act ? c : 1.0f;
+  r.s = act ? t * c : 0.0f;
+  r.ex = act ? ex : 1.0f;
+  r.ey = act ? ey : 0.0f;
+  return r;
+}
+
 // With a = s e (precomputed once per rotation: RotA = {c, Re a, Im a}):
 // right action (X J):  x_i' = c x_i - conj(a) x_j,  x_j' = a x_i + c x_j;
 // left action (J^H X): x_i' = c x_i - a x_j,        x_j' = conj(a) x_i + c x_j.
+template <typename R>
 struct RotA {
-  double c, ax, ay;
+  R c, ax, ay;
 };
-__device__ inline RotA rot_a(const Rot& r) { return RotA{r.c, r.s * r.ex, r.s * r.ey}; }
-__device__ inline void rot_right(const RotA& r, double2& xi, double2& xj) {
-  const double ax = r.ax, ay = r.ay;
-  const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, ay * xj.y)), fma(r.c, xi.y, fma(ay, xj.x, -ax * xj.y)));
-  xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, -ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, ay * xi.x)));
+template <typename R>
+__device__ inline RotA<R> rot_a(const Rot<R>& r) { return RotA<R>{r.c, r.s * r.ex, r.s * r.ey}; }
+template <typename R, typename C>
+__device__ inline void rot_right(const RotA<R>& r, C& xi, C& xj) {
+  const R ax = r.ax, ay = r.ay;
+  const C ni(fma(r.c, xi.x, -fma(ax, xj.x, ay * xj.y)), fma(r.c, xi.y, fma(ay, xj.x, -ax * xj.y)));
+  xj = C(fma(r.c, xj.x, fma(ax, xi.x, -ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, ay * xi.x)));
   xi = ni;
 }
-__device__ inline void rot_left(const RotA& r, double2& xi, double2& xj) {
-  const double ax = r.ax, ay = r.ay;
-  const double2 ni = make_double2(fma(r.c, xi.x, -fma(ax, xj.x, -ay * xj.y)), fma(r.c, xi.y, -fma(ax, xj.y, ay * xj.x)));
-  xj = make_double2(fma(r.c, xj.x, fma(ax, xi.x, ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, -ay * xi.x)));
+template <typename R, typename C>
+__device__ inline void rot_left(const RotA<R>& r, C& xi, C& xj) {
+  const R ax = r.ax, ay = r.ay;
+  const C ni(fma(r.c, xi.x, -fma(ax, xj.x, -ay * xj.y)), fma(r.c, xi.y, -fma(ax, xj.y, ay * xj.x)));
+  xj = C(fma(r.c, xj.x, fma(ax, xi.x, ay * xi.y)), fma(r.c, xj.y, fma(ax, xi.y, -ay * xi.x)));
   xi = ni;
 }
 
@@ -265,30 +323,33 @@ __device__ inline int rr_pair_of(int c, int round) {
 // diagonal and the next round's pair entries are handed on through small
 // double-buffered arrays.
 constexpr int ROT_THREADS = 512;
-template <int JP>
-__global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
+template <int JP, typename R>
+__global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs<R> a) {
+  using T = JT<R>;
+  using C = typename T::C;
+  using V4 = typename T::V4;
   constexpr int GS = JP + 1, NP = JP / 2, NB = JP / 16, JOBS = NP * NP / 256;
   static_assert(NP * NP % 256 == 0, "block jobs must tile a wave group");
-  __shared__ double2 G[JP][GS];
-  __shared__ double2 V[JP][GS];
-  __shared__ double dd[2][JP];
-  __shared__ double2 od[2][NP];
+  __shared__ C G[JP][GS];
+  __shared__ C V[JP][GS];
+  __shared__ R dd[2][JP];
+  __shared__ C od[2][NP];
   __shared__ unsigned char tb_i[JP - 1][NP], tb_j[JP - 1][NP], tb_q[JP - 1][JP];
-  __shared__ RotA rp[NP];
+  __shared__ RotA<R> rp[NP];
   __shared__ int any_flag;
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double2* part = a.part + (int64_t)p * a.n_gchunks * JP * JP;
+  const C* part = a.part + (int64_t)p * a.n_gchunks * JP * JP;
   for (int e = tid; e < JP * JP; e += ROT_THREADS) {
     // partials summed in chunk order; loads issued eight at a time
-    double2 s = make_double2(0.0, 0.0);
+    C s(0, 0);
     for (int c0 = 0; c0 < a.n_gchunks; c0 += 8) {
-      double2 t[8];
+      C t[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        t[u] = c0 + u < a.n_gchunks ? part[(int64_t)(c0 + u) * JP * JP + e] : make_double2(0.0, 0.0);
+        t[u] = c0 + u < a.n_gchunks ? part[(int64_t)(c0 + u) * JP * JP + e] : C(0, 0);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         s.x += t[u].x;
@@ -297,7 +358,7 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
     }
     const int i = e / JP, j = e % JP;
     G[i][j] = s;
-    V[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    V[i][j] = T::mk(i == j ? 1 : 0, 0);
   }
   if (tid == 0) any_flag = 0;
   // Inner schedule tables: members of pair q and the pair of column c, per
@@ -331,19 +392,19 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   for (int e = tid; e < JP * JP; e += ROT_THREADS) {
     const int i = e / JP, j = e % JP;
     if (i < j && (full || (i < NP && j >= NP)) &&
-        rot_active(G[i][i].x, G[j][j].x, G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y, a.tol, a.neg2))
+        rot_active<R>(G[i][i].x, G[j][j].x, G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y, a.tol, a.neg2))
       any_flag = 1;
   }
   for (int c = tid; c < JP; c += ROT_THREADS) dd[0][c] = G[c][c].x;
   for (int q = tid; q < NP; q += ROT_THREADS) od[0][q] = G[tb_i[0][q]][tb_j[0][q]];
   __syncthreads();
   if (!any_flag) return;
-  const double tol_in = 0.5 * a.tol, neg2 = a.neg2;
+  const R tol_in = R(0.5) * a.tol, neg2 = a.neg2;
   const int rounds = a.max_inner * n_in;
   const bool g_waves = w < 4;          // wave-uniform role
   const int t = tid & 255;
   int buf = 0, round = 0;
-  for (int R = 0; R < rounds; ++R) {
+  for (int it = 0; it < rounds; ++it) {
     const int nround = round + 1 == n_in ? 0 : round + 1;
     // the round's rotations, once each
     if (tid < NP) {
@@ -353,14 +414,14 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
     __syncthreads();
     const int pb = t % NP;
     const int ib = tb_i[round][pb], jb = tb_j[round][pb];
-    const RotA rb = rp[pb];
+    const RotA<R> rb = rp[pb];
     if (g_waves) {
 #pragma unroll
       for (int k = 0; k < JOBS; ++k) {
         const int pa = (t + 256 * k) / NP;
         const int ia = tb_i[round][pa], ja = tb_j[round][pa];
-        const RotA ra = rp[pa];
-        double2 g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
+        const RotA<R> ra = rp[pa];
+        C g00 = G[ia][ib], g01 = G[ia][jb], g10 = G[ja][ib], g11 = G[ja][jb];
         rot_right(rb, g00, g01);
         rot_right(rb, g10, g11);
         rot_left(ra, g00, g10);
@@ -386,7 +447,7 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
       for (int k = 0; k < JOBS; ++k) {
         const int pa = (t + 256 * k) / NP;
         const int ia = tb_i[round][pa], ja = tb_j[round][pa];
-        double2 v0 = V[ia][ib], v1 = V[ia][jb], v2 = V[ja][ib], v3 = V[ja][jb];
+        C v0 = V[ia][ib], v1 = V[ia][jb], v2 = V[ja][ib], v3 = V[ja][jb];
         rot_right(rb, v0, v1);
         rot_right(rb, v2, v3);
         V[ia][ib] = v0;
@@ -405,36 +466,36 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
   const int rend = min(a.len, rbeg + a.rows_per_chunk);
   const int ntiles = (rend - rbeg + TR - 1) / TR;
   constexpr int KS = JP / 4, NW = ROT_THREADS / 64;
-  double2 cur[KS], nxt[KS];
+  C cur[KS], nxt[KS];
   const int m = lane & 15, ksub = lane >> 4;
-  auto load_tile_regs = [&](int tt, double2 (&v)[KS]) {
+  auto load_tile_regs = [&](int tt, C (&v)[KS]) {
     const int row = rbeg + tt * TR + m;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int col = pair_col<JP>(4 * ks + ksub, bi, bj);
-      v[ks] = row < rend ? a.x[(int64_t)col * a.ldx + row] : make_double2(0.0, 0.0);
+      v[ks] = row < rend ? a.x[(int64_t)col * a.ldx + row] : C(0, 0);
     }
   };
   if (w < ntiles) load_tile_regs(w, cur);
   for (int tt = w; tt < ntiles; tt += NW) {
     if (tt + NW < ntiles) load_tile_regs(tt + NW, nxt);
-    double4_t cr[NB], ci[NB];
+    V4 cr[NB], ci[NB];
 #pragma unroll
     for (int nt = 0; nt < NB; ++nt) {
-      cr[nt] = double4_t{0, 0, 0, 0};
-      ci[nt] = double4_t{0, 0, 0, 0};
+      cr[nt] = V4{0, 0, 0, 0};
+      ci[nt] = V4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const double2 y = cur[ks];
+      const C y = cur[ks];
       const int k = 4 * ks + ksub;
 #pragma unroll
       for (int nt = 0; nt < NB; ++nt) {
-        const double2 v = V[k][nt * 16 + m];
-        cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.x, cr[nt], 0, 0, 0);
-        cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, v.y, cr[nt], 0, 0, 0);
-        ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, v.y, ci[nt], 0, 0, 0);
-        ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, v.x, ci[nt], 0, 0, 0);
+        const C v = V[k][nt * 16 + m];
+        cr[nt] = T::mma(y.x, v.x, cr[nt]);
+        cr[nt] = T::mma(-y.y, v.y, cr[nt]);
+        ci[nt] = T::mma(y.x, v.y, ci[nt]);
+        ci[nt] = T::mma(y.y, v.x, ci[nt]);
       }
     }
     const int row0 = rbeg + tt * TR;
@@ -442,10 +503,9 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs a) {
     for (int nt = 0; nt < NB; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + f64_row(lane, r);
+        const int row = row0 + T::orow(lane, r);
         const int col = nt * 16 + m;
-        if (row < rend)
-          a.x[(int64_t)pair_col<JP>(col, bi, bj) * a.ldx + row] = make_double2(cr[nt][r], ci[nt][r]);
+        if (row < rend) a.x[(int64_t)pair_col<JP>(col, bi, bj) * a.ldx + row] = T::mk(cr[nt][r], ci[nt][r]);
       }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) cur[ks] = nxt[ks];
@@ -561,7 +621,8 @@ size_t jacobi_work_bytes(const JacobiPlan& pl) {
          256;
 }
 
-static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bool first) {
+template <typename R>
+static void launch_sweep(const JacobiPlan& pl, JacArgs<R> a, hipStream_t stream, bool first) {
   hipLaunchKernelGGL(k_jac_roll, dim3(1), dim3(256), 0, stream, a.rot_prev, a.rot_cur, a.rot_count, pl.nbp,
                      first ? 1 : 0);
   HIP_LAUNCH_OK();
@@ -575,19 +636,21 @@ static void launch_sweep(const JacobiPlan& pl, JacArgs a, hipStream_t stream, bo
     {
       Probe pr(kKcJacGram, stream, fl, by);
       if (pl.jb == 16)
-        hipExtLaunchKernelGGL(k_jac_gram<32>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(), pr.stop(), 0, a);
+        hipExtLaunchKernelGGL((k_jac_gram<32, R>), dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(),
+                              pr.stop(), 0, a);
       else
-        hipExtLaunchKernelGGL(k_jac_gram<64>, dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(), pr.stop(), 0, a);
+        hipExtLaunchKernelGGL((k_jac_gram<64, R>), dim3(pl.n_pairs, pl.n_gchunks), dim3(256), 0, stream, pr.start(),
+                              pr.stop(), 0, a);
     }
     HIP_LAUNCH_OK();
     {
       Probe pr(kKcJacRotate, stream, fl, 2.0 * by);
       if (pl.jb == 16)
-        hipExtLaunchKernelGGL(k_jac_rotate<32>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, pr.start(),
-                              pr.stop(), 0, a);
+        hipExtLaunchKernelGGL((k_jac_rotate<32, R>), dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream,
+                              pr.start(), pr.stop(), 0, a);
       else
-        hipExtLaunchKernelGGL(k_jac_rotate<64>, dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream, pr.start(),
-                              pr.stop(), 0, a);
+        hipExtLaunchKernelGGL((k_jac_rotate<64, R>), dim3(pl.n_pairs, pl.n_chunks), dim3(ROT_THREADS), 0, stream,
+                              pr.start(), pr.stop(), 0, a);
     }
     HIP_LAUNCH_OK();
   }
@@ -614,7 +677,7 @@ std::vector<SweepGraph> g_graphs;
 std::mutex g_graph_mu;
 }  // namespace
 
-static hipGraphExec_t sweep_graph(const JacobiPlan& pl, const JacArgs& a, void* work, hipStream_t stream) {
+static hipGraphExec_t sweep_graph(const JacobiPlan& pl, const JacArgs<double>& a, void* work, hipStream_t stream) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   for (auto& g : g_graphs)
     if (g.len == pl.len && g.cnt == pl.cnt && g.jb == pl.jb && g.inner == a.max_inner && g.x == a.x &&
@@ -640,9 +703,11 @@ static hipGraphExec_t sweep_graph(const JacobiPlan& pl, const JacArgs& a, void* 
   return exec;
 }
 
-int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev, int* rot_count_host,
-               double fro2, hipStream_t stream, int max_sweeps, double tol) {
-  JacArgs a;
+template <typename R>
+static int jacobi_run_t(const JacobiPlan& pl, typename JT<R>::C* x, void* work, int* rot_count_dev,
+                        int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol) {
+  using C = typename JT<R>::C;
+  JacArgs<R> a;
   a.x = x;
   a.ldx = pl.ldx;
   a.len = pl.len;
@@ -653,23 +718,28 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
   a.n_gchunks = pl.n_gchunks;
   a.round = 0;
   char* w = reinterpret_cast<char*>(work);
-  a.part = reinterpret_cast<double2*>(w);
-  w += (size_t)pl.n_pairs * pl.n_gchunks * (2 * pl.jb) * (2 * pl.jb) * sizeof(double2);
+  a.part = reinterpret_cast<C*>(w);
+  w += (size_t)pl.n_pairs * pl.n_gchunks * (2 * pl.jb) * (2 * pl.jb) * sizeof(C);
   a.rot_prev = reinterpret_cast<int*>(w);
   a.rot_cur = a.rot_prev + pl.nbp;
   a.rot_count = rot_count_dev;
-  a.tol = tol > 0.0 ? tol : 16.0 * 1.11e-16 * std::sqrt((double)std::max(pl.len, 16));
+  const double u = JT<R>::u;
+  a.tol = (R)(tol > 0.0 ? tol : 16.0 * u * std::sqrt((double)std::max(pl.len, 16)));
   // columns shorter than delta ||X||_F (delta = 8 u sqrt(len)) are numerically
-  // zero: below the absolute accuracy of any fp64 SVD, and they must not be
-  // required to be mutually orthogonal (a wide matrix has more columns than
-  // its rank)
-  const double delta = 8.0 * 1.11e-16 * std::sqrt((double)pl.len);
-  a.neg2 = delta * delta * std::max(fro2, 1e-300);
+  // zero: below the absolute accuracy of any SVD in this precision, and they
+  // must not be required to be mutually orthogonal (a wide matrix has more
+  // columns than its rank)
+  const double delta = 8.0 * u * std::sqrt((double)pl.len);
+  a.neg2 = (R)(delta * delta * std::max(fro2, 1e-300));
   a.max_inner = pl.inner;
-  const bool graphs = use_graphs() && pl.nbp > 4;
+  bool graphs = false;
+  if constexpr (std::is_same<R, double>::value) graphs = use_graphs() && pl.nbp > 4;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
-    if (graphs && sweep > 1) {
-      HIP_OK(hipGraphLaunch(sweep_graph(pl, a, work, stream), stream));
+    if constexpr (std::is_same<R, double>::value) {
+      if (graphs && sweep > 1)
+        HIP_OK(hipGraphLaunch(sweep_graph(pl, a, work, stream), stream));
+      else
+        launch_sweep(pl, a, stream, sweep == 1);
     } else {
       launch_sweep(pl, a, stream, sweep == 1);
     }
@@ -680,6 +750,16 @@ int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
     if (*rot_count_host == 0) return sweep;
   }
   fail(RCS_ERR_NUMERIC, "one-sided Jacobi SVD did not converge");
+}
+
+int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev, int* rot_count_host, double fro2,
+               hipStream_t stream, int max_sweeps, double tol) {
+  return jacobi_run_t<double>(pl, x, work, rot_count_dev, rot_count_host, fro2, stream, max_sweeps, tol);
+}
+
+int jacobi_run_f32(const JacobiPlan& pl, float2* x, void* work, int* rot_count_dev, int* rot_count_host, double fro2,
+                   hipStream_t stream, int max_sweeps, double tol) {
+  return jacobi_run_t<float>(pl, x, work, rot_count_dev, rot_count_host, fro2, stream, max_sweeps, tol);
 }
 
 void jacobi_init_attributes() {}

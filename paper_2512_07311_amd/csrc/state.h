@@ -83,6 +83,7 @@ struct rcs_state_s {
   int n_moves = 0;
   int n_precond = 0, n_precond_fallback = 0;   // preconditioned splits, and those redone plainly
   int n_moves_cholqr = 0;                        // centre moves done by CholeskyQR
+  int n_svd_f32 = 0, n_svd_f32_redone = 0;       // fp32 Jacobi splits, and those redone in fp64
   double nominal_svd_flops = 0.0, nominal_qr_flops = 0.0;
   std::vector<rcs::SpectrumRecord> spectra;
   std::vector<rcs::UpdateRecord> updates;
