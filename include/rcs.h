@@ -156,7 +156,8 @@ typedef struct {
  * from the same preconditioned matrix.  In RCS_RANK_LEARNED mode a cut the
  * network predicts to be cap-limited skips the randomized SVD (whose
  * sketch cannot resolve the spectrum at the cap more cheaply) and goes to
- * this split. */
+ * this split; a cut it predicts to be eps-limited tries the randomized SVD
+ * and, if the judge rejects it, the fp64 split directly. */
 typedef enum { RCS_SVD_F64 = 0, RCS_SVD_F32 = 1 } rcs_svd_precision;
 
 /* Fills *opts with defaults: C128, FULL_SVD, tau 1e-6, p 16, q 2, null

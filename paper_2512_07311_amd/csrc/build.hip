@@ -1103,6 +1103,7 @@ struct UpdateCtx {
   RsvdWork rw;
   DevBuf M;
   int chi_cap = 0;
+  bool pred_capped = true;          // learned mode: the network predicted k_hat >= cap for this update
   double* dev_scalars() { return scal2.as<double>(); }
 };
 
@@ -1172,6 +1173,7 @@ static bool randomized_split(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int
   const int l = std::min(k_hat + std::max(0, o.rsvd_p), m);
   rec.k_hat = k_hat;
   rec.l = l;
+  ctx.pred_capped = k_hat >= cap;
   if (l >= m) return false;   // the sketch would cover the whole space: plain split
   // predicted cap-limited cut with the fp32 full SVD available: no sketch
   if (o.svd_f32 && o.rank_mode == RCS_RANK_LEARNED && k_hat >= cap) return false;
@@ -1280,6 +1282,7 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
   ws.T.ensure((size_t)4 * dl * dr * sizeof(double2));
   contract_two_site(st.site[i], st.site[i + 1], ws.T.as<double2>(), dl, dm, dr, precision, s);
   const size_t n_log = st.rsvd_log.size();
+  ctx.pred_capped = true;
   if (ctx.o && ctx.o->rank_mode != RCS_RANK_FULL_SVD &&
       randomized_split(st, ws, ctx, i, gate16, cap_eff, eps, cycle, log_spectra))
     return;
@@ -1311,8 +1314,11 @@ static void two_site_update(rcs_state_s& st, BuildWork& ws, UpdateCtx& ctx, int 
   std::vector<double> spec;
   SplitResult r{};
   int ldw = pl.ldx, p_row = pl.cnt, side = orient;
-  if (precond && svd_split_chol(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr, r, &ldw,
-                                ctx.o && ctx.o->svd_f32)) {
+  // fp32 first, unless the network predicted an eps-limited rank (the fp32
+  // result would be redone in fp64)
+  const bool try32 =
+      ctx.o && ctx.o->svd_f32 && (ctx.o->rank_mode != RCS_RANK_LEARNED || ctx.pred_capped);
+  if (precond && svd_split_chol(st, ws, pl, cap_eff, eps, true, log_spectra ? &spec : nullptr, r, &ldw, try32)) {
     // orthonormal factor on X's column side: the other orientation's layout
     side = 3 - orient;
     p_row = len;
