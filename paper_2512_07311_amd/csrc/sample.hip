@@ -10,6 +10,17 @@
 // the branch and records the bit.  The next site reads its V rows straight
 // out of W at the chosen half (no copy).  The last site has a single column,
 // whose |w|^2 is p(b).
+//
+// Because the tensors right of the current site are right-canonical, the two
+// branch probabilities of a shot add up to the squared norm of its row
+// vector, p0 + p1 = ||v||^2, which the previous site already produced (the
+// partial norms of the chosen half).  At the sites past the first whose
+// GEMM is large, sampling therefore computes W^0 for every shot, decides
+// with u ||v||^2 >= p0, and computes W^1 = v A^1 only for the shots that
+// chose 1 (compacted row list): 1.5 instead of 2 shot GEMMs per site on
+// average.  Both W halves keep the values the two-branch GEMM gives, and the
+// decision differs from u (p0 + p1) >= p0 only where the two sides lie
+// within the state's canonical residual of each other.
 #include <mutex>
 
 #include "gemm_f64.h"
@@ -19,25 +30,33 @@
 namespace rcs {
 
 struct ChainArgs {
-  const double2* wprev;  // S x 2*dl from the previous site (null at site 0)
-  const int8_t* sel;     // per-shot chosen half at the previous site
-  const double2* site;   // A_k, [s][a][b], dl x dr
-  double2* wout;         // S x 2*dr
-  double* part;          // [2][S][ntiles] partial |w|^2
-  int S, dl, dr, ntiles;
+  const double2* wprev = nullptr;  // S x 2*dl from the previous site (null at site 0)
+  const int8_t* sel = nullptr;     // per-shot chosen half at the previous site
+  const double2* site = nullptr;   // A_k, [s][a][b], dl x dr
+  double2* wout = nullptr;         // S x 2*dr
+  double* part = nullptr;          // [2][S][ntiles] partial |w|^2
+  int S = 0, dl = 0, dr = 0, ntiles = 0;
+  int s_fixed = -1;                // >= 0: only this half (grid z = 1); else half = blockIdx.z
+  const int* rows = nullptr;       // compacted shot list (logical row -> shot), or null
+  const int* nrows = nullptr;      // its length (device), when rows is set
+  int* reset = nullptr;            // zeroed by the first thread of the launch, or null
 };
 
 __device__ inline void chain_gemm_tile(const ChainArgs& a, int tn, int tm, int s, SmemC64& sm,
                                        double (*rowsum)[GT_M]) {
   const int m0 = tm * GT_M, n0 = tn * GT_N;
+  const int M = a.rows ? *a.nrows : a.S;       // logical rows
+  if (m0 >= M) return;                         // whole workgroup: nothing to do
   const int dl = a.dl, dr = a.dr;
+  auto shot = [&](int m) -> int { return a.rows ? a.rows[m] : m; };
   auto fa = [&](int m, int k) -> double2 {
     if (a.wprev == nullptr) return (k == 0) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-    return a.wprev[(int64_t)m * 2 * dl + (int64_t)a.sel[m] * dl + k];
+    const int sm_ = shot(m);
+    return a.wprev[(int64_t)sm_ * 2 * dl + (int64_t)a.sel[sm_] * dl + k];
   };
   const double2* bs = a.site + (int64_t)s * dl * dr;
   auto fb = [&](int k, int n) -> double2 { return bs[(int64_t)k * dr + n]; };
-  LoadA<decltype(fa), true> la{fa, m0, a.S, dl};
+  LoadA<decltype(fa), true> la{fa, m0, M, dl};
   LoadB<decltype(fb), true> lb{fb, n0, dl, dr};
   AccC64 acc;
   acc_zero(acc);
@@ -60,8 +79,8 @@ __device__ inline void chain_gemm_tile(const ChainArgs& a, int tn, int tm, int s
         int m = m0 + wm + mt * 16 + f64_row(lane, r);
         int n = n0 + wn + nt * 16 + (lane & 15);
         double re = acc.re[mt][nt][r], im = acc.im[mt][nt][r];
-        if (m < a.S && n < dr) {
-          a.wout[(int64_t)m * 2 * dr + (int64_t)s * dr + n] = make_double2(re, im);
+        if (m < M && n < dr) {
+          a.wout[(int64_t)shot(m) * 2 * dr + (int64_t)s * dr + n] = make_double2(re, im);
           rs[mt][r] += re * re + im * im;
         }
       }
@@ -79,14 +98,15 @@ __device__ inline void chain_gemm_tile(const ChainArgs& a, int tn, int tm, int s
   __syncthreads();
   if (tid < GT_M) {
     int m = m0 + tid;
-    if (m < a.S) a.part[((int64_t)s * a.S + m) * a.ntiles + tn] = rowsum[0][tid] + rowsum[1][tid];
+    if (m < M) a.part[((int64_t)s * a.S + shot(m)) * a.ntiles + tn] = rowsum[0][tid] + rowsum[1][tid];
   }
 }
 
 __global__ __launch_bounds__(GT_THREADS) void k_chain_gemm(ChainArgs a) {
   __shared__ SmemC64 sm;
   __shared__ double rowsum[2][GT_M];
-  chain_gemm_tile(a, blockIdx.x, blockIdx.y, blockIdx.z, sm, rowsum);
+  if (a.reset && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *a.reset = 0;
+  chain_gemm_tile(a, blockIdx.x, blockIdx.y, a.s_fixed >= 0 ? a.s_fixed : (int)blockIdx.z, sm, rowsum);
 }
 
 // Grouped form for a batch of states: group g owns tiles [tile0[g],
@@ -108,19 +128,35 @@ __global__ __launch_bounds__(GT_THREADS) void k_chain_gemm_grouped(const ChainGr
 }
 
 struct DecideArgs {
-  const double* part;
-  int S, ntiles, site, qubit, last, mode;
-  uint64_t seed, shot0;
-  int8_t* sel;
-  uint64_t* bits;          // mode 0 output
-  double* log2p;           // mode 0 output (nullable)
-  const uint64_t* inbits;  // mode 1 input
-  const double2* wlast;    // S x 2 at the last site
-  double2* amps;           // mode 1 output
+  const double* part = nullptr;
+  int S = 0, ntiles = 0, site = 0, qubit = 0, last = 0, mode = 0;
+  uint64_t seed = 0, shot0 = 0;
+  int8_t* sel = nullptr;
+  uint64_t* bits = nullptr;          // mode 0 output
+  double* log2p = nullptr;           // mode 0 output (nullable)
+  const uint64_t* inbits = nullptr;  // mode 1 input
+  const double2* wlast = nullptr;    // S x 2 at the last site
+  double2* amps = nullptr;           // mode 1 output
+  double* vnorm = nullptr;           // mode 0: ||v||^2 of each shot's next row (nullable)
+  int split = 0;                     // only W^0 was computed: decide with u ||v||^2 >= p0
+  int* n1 = nullptr;                 // split: length of the list of shots that chose 1
+  int* idx1 = nullptr;               // split: that list
 };
 
 __device__ inline void decide_one(const DecideArgs& a, int m) {
-  if (a.mode == 0) {
+  if (a.mode == 0 && a.split) {
+    double p0 = 0.0;
+    const double* q0 = a.part + (int64_t)m * a.ntiles;
+    for (int t = 0; t < a.ntiles; ++t) p0 += q0[t];
+    const double u = shot_uniform(a.seed, a.shot0 + (uint64_t)m, a.site);
+    const int b = (u * a.vnorm[m] >= p0) ? 1 : 0;
+    a.bits[m] |= (uint64_t)b << a.qubit;
+    a.sel[m] = (int8_t)b;
+    if (b == 0)
+      a.vnorm[m] = p0;
+    else
+      a.idx1[atomicAdd(a.n1, 1)] = m;
+  } else if (a.mode == 0) {
     double p0 = 0.0, p1 = 0.0;
     const double* q0 = a.part + (int64_t)m * a.ntiles;
     const double* q1 = a.part + ((int64_t)a.S + m) * a.ntiles;
@@ -133,6 +169,7 @@ __device__ inline void decide_one(const DecideArgs& a, int m) {
     const uint64_t bit = (uint64_t)b << a.qubit;
     a.bits[m] = (a.site == 0) ? bit : (a.bits[m] | bit);
     a.sel[m] = (int8_t)b;
+    if (a.vnorm) a.vnorm[m] = b ? p1 : p0;
     if (a.last && a.log2p) a.log2p[m] = log2(b ? p1 : p0);
   } else {
     const int b = (int)((a.inbits[m] >> a.qubit) & 1ull);
@@ -144,6 +181,18 @@ __device__ inline void decide_one(const DecideArgs& a, int m) {
 __global__ void k_decide(DecideArgs a) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < a.S) decide_one(a, m);
+}
+
+// ||v||^2 of the shots that chose 1 at a split site: their W^1 partial
+// norms, summed in the same order as the two-branch decision sums p1.
+__global__ void k_vnorm1(const double* part, int S, int ntiles, const int* idx1, const int* n1, double* vnorm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n1) return;
+  const int m = idx1[i];
+  const double* q1 = part + ((int64_t)S + m) * ntiles;
+  double p1 = 0.0;
+  for (int t = 0; t < ntiles; ++t) p1 += q1[t];
+  vnorm[m] = p1;
 }
 
 __global__ void k_decide_grouped(const DecideArgs* groups) {
@@ -160,22 +209,37 @@ int state_max_bond(const rcs_state_s& st) {
 
 // Bytes of sampler workspace for S shots per pass at maximum bond maxd:
 // two ping-pong W buffers (S x 2 maxd complex), the per-shot partial norms
-// of every column tile of both branches, and the chosen branch per shot.
+// of every column tile of both branches, the chosen branch per shot, the
+// per-shot ||v||^2, the list of shots that chose 1 and its length.  The
+// chosen branch is double-buffered by site parity: a split site's W^1 GEMM
+// runs after its decision and still reads the previous site's choice.
 size_t chain_work_bytes(int64_t S, int maxd) {
   const int ntiles = ceil_div(maxd, GT_N);
   return 2 * round_up((size_t)S * 2 * maxd * sizeof(double2), 256) +
-         round_up((size_t)2 * S * ntiles * sizeof(double), 256) + round_up((size_t)S, 256);
+         round_up((size_t)2 * S * ntiles * sizeof(double), 256) + 2 * round_up((size_t)S, 256) +
+         round_up((size_t)S * sizeof(double), 256) + round_up((size_t)S * sizeof(int), 256) + 256;
 }
 
 ChainBuffers chain_buffers_in(char* base, int64_t S, int maxd) {
   const int ntiles = ceil_div(maxd, GT_N);
   ChainBuffers b;
   b.S0 = S;
+  size_t off = 0;
   const size_t wb = round_up((size_t)S * 2 * maxd * sizeof(double2), 256);
   b.w[0] = reinterpret_cast<double2*>(base);
   b.w[1] = reinterpret_cast<double2*>(base + wb);
-  b.part = reinterpret_cast<double*>(base + 2 * wb);
-  b.sel = reinterpret_cast<int8_t*>(base + 2 * wb + round_up((size_t)2 * S * ntiles * sizeof(double), 256));
+  off = 2 * wb;
+  b.part = reinterpret_cast<double*>(base + off);
+  off += round_up((size_t)2 * S * ntiles * sizeof(double), 256);
+  b.sel = reinterpret_cast<int8_t*>(base + off);
+  off += round_up((size_t)S, 256);
+  b.sel2 = reinterpret_cast<int8_t*>(base + off);
+  off += round_up((size_t)S, 256);
+  b.vnorm = reinterpret_cast<double*>(base + off);
+  off += round_up((size_t)S * sizeof(double), 256);
+  b.idx1 = reinterpret_cast<int*>(base + off);
+  off += round_up((size_t)S * sizeof(int), 256);
+  b.n1 = reinterpret_cast<int*>(base + off);
   return b;
 }
 
@@ -191,13 +255,19 @@ void run_chain(rcs_state_s& st, uint64_t first_shot, uint64_t n_shots, uint64_t 
   st.wbuf[0].ensure((size_t)S0 * 2 * maxd * sizeof(double2));
   st.wbuf[1].ensure((size_t)S0 * 2 * maxd * sizeof(double2));
   st.part.ensure((size_t)2 * S0 * ntiles_max * sizeof(double));
-  st.sel.ensure((size_t)S0);
+  st.sel.ensure((size_t)2 * S0);
+  st.vnorm.ensure((size_t)S0 * sizeof(double));
+  st.idx1.ensure((size_t)S0 * sizeof(int) + 256);
   ChainBuffers b;
   b.S0 = S0;
   b.w[0] = st.wbuf[0].as<double2>();
   b.w[1] = st.wbuf[1].as<double2>();
   b.part = st.part.as<double>();
   b.sel = st.sel.as<int8_t>();
+  b.sel2 = st.sel.as<int8_t>() + S0;
+  b.vnorm = st.vnorm.as<double>();
+  b.idx1 = st.idx1.as<int>();
+  b.n1 = reinterpret_cast<int*>(st.idx1.as<char>() + round_up((size_t)S0 * sizeof(int), 256));
   run_chain_with(st, b, first_shot, n_shots, seed, mode, bits_dev, log2p_dev, in_bits_dev, amps_dev);
 }
 
@@ -209,9 +279,11 @@ void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_sho
   for (uint64_t b0 = 0; b0 < n_shots; b0 += (uint64_t)S0) {
     const int S = (int)std::min<uint64_t>((uint64_t)S0, n_shots - b0);
     for (int k = 0; k < st.n; ++k) {
+      int8_t* sel_prev = (k & 1) ? buf.sel : buf.sel2;   // written by site k - 1
+      int8_t* sel_cur = (k & 1) ? buf.sel2 : buf.sel;
       ChainArgs ca;
       ca.wprev = (k == 0) ? nullptr : buf.w[(k - 1) & 1];
-      ca.sel = buf.sel;
+      ca.sel = sel_prev;
       ca.site = st.site[k];
       ca.wout = buf.w[k & 1];
       ca.part = buf.part;
@@ -219,12 +291,20 @@ void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_sho
       ca.dl = st.dims[k];
       ca.dr = st.dims[k + 1];
       ca.ntiles = ceil_div(ca.dr, GT_N);
-      dim3 grid(ca.ntiles, ceil_div(S, GT_M), 2);
+      // split sites: past the first, not the last, GEMM large enough
+      const bool split = mode == 0 && k > 0 && k < st.n - 1 && (int64_t)ca.dl * ca.dr >= 1024 &&
+                         buf.vnorm && buf.idx1 && buf.n1;
+      if (split) {
+        ca.s_fixed = 0;
+        ca.reset = buf.n1;
+      }
+      dim3 grid(ca.ntiles, ceil_div(S, GT_M), split ? 1 : 2);
       {
-        // algorithmic: 2 complex GEMMs S x dl x dr (8 real flops per complex
-        // multiply-add); HBM: site tensor + V rows read + W written
-        const double fl = 16.0 * S * (double)ca.dl * ca.dr;
-        const double by = 16.0 * (2.0 * ca.dl * ca.dr + (double)S * ca.dl + 2.0 * S * ca.dr);
+        // algorithmic: complex GEMMs S x dl x dr per half (8 real flops per
+        // complex multiply-add); HBM: site tensor + V rows read + W written
+        const double halves = split ? 1.0 : 2.0;
+        const double fl = 8.0 * halves * S * (double)ca.dl * ca.dr;
+        const double by = 16.0 * (halves * ca.dl * ca.dr + (double)S * ca.dl + halves * S * ca.dr);
         Probe pr(probe ? kKcChainGemm : -1, st.stream, fl, by);
         hipExtLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, pr.start(), pr.stop(), 0, ca);
       }
@@ -239,14 +319,36 @@ void run_chain_with(rcs_state_s& st, const ChainBuffers& buf, uint64_t first_sho
       da.mode = mode;
       da.seed = seed;
       da.shot0 = first_shot + b0;
-      da.sel = buf.sel;
+      da.sel = sel_cur;
       da.bits = bits_dev ? bits_dev + b0 : nullptr;
       da.log2p = log2p_dev ? log2p_dev + b0 : nullptr;
       da.inbits = in_bits_dev ? in_bits_dev + b0 : nullptr;
       da.wlast = ca.wout;
       da.amps = amps_dev ? reinterpret_cast<double2*>(amps_dev) + b0 : nullptr;
+      da.vnorm = mode == 0 ? buf.vnorm : nullptr;
+      da.split = split ? 1 : 0;
+      da.n1 = buf.n1;
+      da.idx1 = buf.idx1;
       hipLaunchKernelGGL(k_decide, dim3(ceil_div(S, 256)), dim3(256), 0, st.stream, da);
       HIP_LAUNCH_OK();
+      if (split) {
+        // W^1 for the shots that chose 1 (work about half the W^0 GEMM's)
+        ChainArgs cb = ca;
+        cb.s_fixed = 1;
+        cb.reset = nullptr;
+        cb.rows = buf.idx1;
+        cb.nrows = buf.n1;
+        {
+          const double fl = 8.0 * 0.5 * S * (double)ca.dl * ca.dr;
+          const double by = 16.0 * (ca.dl * ca.dr + 0.5 * S * ca.dl + 0.5 * S * ca.dr);
+          Probe pr(probe ? kKcChainGemm : -1, st.stream, fl, by);
+          hipExtLaunchKernelGGL(k_chain_gemm, grid, dim3(GT_THREADS), 0, st.stream, pr.start(), pr.stop(), 0, cb);
+        }
+        HIP_LAUNCH_OK();
+        hipLaunchKernelGGL(k_vnorm1, dim3(ceil_div(S, 256)), dim3(256), 0, st.stream, ca.part, S, ca.ntiles,
+                           buf.idx1, buf.n1, buf.vnorm);
+        HIP_LAUNCH_OK();
+      }
     }
   }
 }

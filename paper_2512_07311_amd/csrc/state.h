@@ -89,7 +89,7 @@ struct rcs_state_s {
   std::vector<rcs::UpdateRecord> updates;
   std::vector<rcs::RsvdRecord> rsvd_log;
   // sampler workspace (grown on demand)
-  rcs::DevBuf wbuf[2], part, sel, lastp;
+  rcs::DevBuf wbuf[2], part, sel, lastp, vnorm, idx1;
 };
 
 namespace rcs {
@@ -105,7 +105,11 @@ size_t site_capacity(const rcs_state_s& st, int k);
 struct ChainBuffers {
   double2* w[2] = {nullptr, nullptr};
   double* part = nullptr;
-  int8_t* sel = nullptr;
+  int8_t* sel = nullptr;     // chosen branch, written at even sites
+  int8_t* sel2 = nullptr;    // chosen branch, written at odd sites
+  double* vnorm = nullptr;   // per-shot ||v||^2 (split sites)
+  int* idx1 = nullptr;       // shots that chose 1 at a split site
+  int* n1 = nullptr;         // their count
   int64_t S0 = 0;
 };
 int state_max_bond(const rcs_state_s& st);
