@@ -674,7 +674,7 @@ struct BuildWork {
   int* host_rot = nullptr;        // pinned
   BuildWork() {
     HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&host_rank), sizeof(RankOut)));
-    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&host_rot), sizeof(int)));
+    HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&host_rot), 2 * sizeof(int)));
   }
   ~BuildWork() {
     if (host_rank) (void)hipHostFree(host_rank);
@@ -967,7 +967,7 @@ void ensure_work(BuildWork& ws, const JacobiPlan& pl, int64_t t_elems) {
   ws.sorted.ensure((size_t)pl.cnt_pad * sizeof(double));
   ws.order.ensure((size_t)pl.cnt_pad * sizeof(int));
   ws.scal.ensure(sizeof(RankOut));
-  ws.rot.ensure(sizeof(int));
+  ws.rot.ensure(2 * sizeof(int));
   if (t_elems > 0) ws.T.ensure((size_t)t_elems * sizeof(double2));
 }
 

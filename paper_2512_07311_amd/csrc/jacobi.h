@@ -22,9 +22,13 @@ JacobiPlan jacobi_plan(int len, int cnt, int jb = 0);
 size_t jacobi_work_bytes(const JacobiPlan& pl);
 void jacobi_init_attributes();
 // Orthogonalises the columns of x in place; returns the number of sweeps
-// (the last one rotates nothing).  fro2 = ||x||_F^2; columns below
+// (the last one rotates nothing, or its largest entering cosine squared is
+// below tol / 100, after which the next would rotate nothing: quadratic
+// convergence).  fro2 = ||x||_F^2; columns below
 // 8 u sqrt(len) ||x||_F count as numerically zero.
 // tol > 0 replaces the default relative orthogonality tolerance 16 u sqrt(len).
+// rot_count_dev and rot_count_host hold two ints (rotation count, largest
+// squared cosine of the sweep as fp32 bits).
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
                int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol = 0.0);
 // The same in fp32 (complex64 columns, u = 2^-24); work as sized by
