@@ -752,7 +752,9 @@ static SplitResult svd_split(rcs_state_s& st, BuildWork& ws, const JacobiPlan& p
                      ws.order.as<int>(), ws.sorted.as<double>(), ws.Wn.as<double2>());
   HIP_LAUNCH_OK();
   // orthonormalise: X <- Wn (3I - Wn^H Wn)/2 (X is free after the gather);
-  // a second step, from X back into Wn, after a loose Jacobi iteration
+  // the Jacobi stops at an absolute floor, so kept columns of small singular
+  // values are orthonormal only to ~floor / (s_i s_j); a second step, from X
+  // back into Wn, after the loose iteration of a centre move
   double2* src = ws.Wn.as<double2>();
   double2* dst = X;
   for (int it = 0; it < (ortho_only ? 2 : 1); ++it) {
@@ -900,9 +902,12 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   out = SplitResult{r.k, r.nnz, sweeps, r.eps_step, r.w, r.nrm};
   if (spectrum_out) spectrum_out->assign(ws.host_sorted.begin(), ws.host_sorted.end());
   const int k = r.k;
-  // kept columns of Y J, normalised: V_k in the sorted basis.  Newton-Schulz
-  // steps make them orthonormal to rounding: one after the fp64 Jacobi
-  // (into Y, free after the gather), two after the fp32 one (Wn -> Y -> Wn).
+  // kept columns of Y J, normalised: V_k in the sorted basis.  The accepted
+  // fp64 split keeps only squared values >= 1e-10 of the weight, far above
+  // the Jacobi's noise floor, so every kept pair is orthogonal to the
+  // relative tolerance and the columns are orthonormal to fp64 accuracy as
+  // they are; after the fp32 Jacobi two Newton-Schulz steps (Wn -> Y -> Wn,
+  // Y is free after the gather) make them orthonormal to fp64 rounding.
   double2* Wn = ws.Wn.as<double2>();
   if (use32)
     RCS_PROBED_LAUNCH(kKcFactor, k_gather_normalize_c64, dim3(ceil_div(py.ldx, 256), k), dim3(256), 0, s, Y32,
@@ -913,7 +918,7 @@ static bool svd_split_chol(rcs_state_s& st, BuildWork& ws, const JacobiPlan& pl,
   HIP_LAUNCH_OK();
   double2* src = Wn;
   double2* dst = Y;
-  for (int it = 0; it < (use32 ? 2 : 1); ++it) {
+  for (int it = 0; it < (use32 ? 2 : 0); ++it) {
     RCS_PROBED_LAUNCH(kKcFactor, k_ns_gram, dim3(ceil_div(k, GT_N), ceil_div(k, GT_M)), dim3(GT_THREADS), 0, s, src,
                        py.ldx, n, k, ws.H.as<double2>());
     HIP_LAUNCH_OK();
