@@ -27,8 +27,8 @@ void jacobi_init_attributes();
 // convergence).  fro2 = ||x||_F^2; columns below
 // 8 u sqrt(len) ||x||_F count as numerically zero.
 // tol > 0 replaces the default relative orthogonality tolerance 16 u sqrt(len).
-// rot_count_dev and rot_count_host hold two ints (rotation count, largest
-// squared cosine of the sweep as fp32 bits).
+// rot_count_dev and rot_count_host hold two ints (rotation count; whether a
+// meeting of the sweep entered with a squared cosine above tol / 100).
 int jacobi_run(const JacobiPlan& pl, double2* x, void* work, int* rot_count_dev,
                int* rot_count_host, double fro2, hipStream_t stream, int max_sweeps, double tol = 0.0);
 // The same in fp32 (complex64 columns, u = 2^-24); work as sized by

@@ -25,7 +25,6 @@
 // sweep that rotates nothing ends the iteration.
 #include <algorithm>
 #include <cstdlib>
-#include <cstring>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -78,7 +77,8 @@ struct JacArgs {
   int* rot_prev;      // [nbp] block rotated during the previous sweep
   int* rot_cur;       // [nbp] block rotated during this sweep
   int* rot_count;
-  unsigned* maxcos2;  // max over the sweep's meetings of |g_ij|^2 / (g_ii g_jj), fp32 bits
+  int* big_cos;       // set when a meeting entered with |g_ij|^2 > qtol g_ii g_jj
+  R qtol;             // squared-cosine level below which the next sweep would rotate nothing
   R tol;              // relative orthogonality tolerance
   R neg2;             // squared column norm below which a column counts as zero
   int max_inner;      // inner two-sided sweeps per pair meeting
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs<R> a) {
   __shared__ unsigned char tb_i[JP - 1][NP], tb_j[JP - 1][NP], tb_q[JP - 1][JP];
   __shared__ RotA<R> rp[NP];
   __shared__ int any_flag;
-  __shared__ unsigned c2_lds;
+  __shared__ int big_lds;
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int bi = rr_block(p, a.round, a.nbp), bj = rr_block(a.nbp - 1 - p, a.round, a.nbp);
   if (pair_skipped(a, bi, bj)) return;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs<R> a) {
   }
   if (tid == 0) {
     any_flag = 0;
-    c2_lds = 0u;
+    big_lds = 0;
   }
   // Inner schedule tables: members of pair q and the pair of column c, per
   // round.  The first outer round of a sweep runs the full round-robin over
@@ -395,22 +395,18 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs<R> a) {
   }
   __syncthreads();
   // only the pairs this meeting's schedule rotates decide whether it acts
-  float c2max = 0.0f;
   for (int e = tid; e < JP * JP; e += ROT_THREADS) {
     const int i = e / JP, j = e % JP;
     if (i < j && (full || (i < NP && j >= NP))) {
       const R gii = G[i][i].x, gjj = G[j][j].x, h2 = G[i][j].x * G[i][j].x + G[i][j].y * G[i][j].y;
       if (rot_active<R>(gii, gjj, h2, a.tol, a.neg2)) any_flag = 1;
-      if (gii > a.neg2 && gjj > a.neg2) c2max = fmaxf(c2max, (float)(h2 / (gii * gjj)));
+      if (gii > a.neg2 && gjj > a.neg2 && h2 > a.qtol * gii * gjj) big_lds = 1;
     }
   }
-  // this meeting's largest squared cosine (non-negative fp32 values order
-  // like their bit patterns)
-  if (chunk == 0 && c2max > 0.0f) atomicMax(&c2_lds, __float_as_uint(c2max));
   for (int c = tid; c < JP; c += ROT_THREADS) dd[0][c] = G[c][c].x;
   for (int q = tid; q < NP; q += ROT_THREADS) od[0][q] = G[tb_i[0][q]][tb_j[0][q]];
   __syncthreads();
-  if (chunk == 0 && tid == 0 && c2_lds != 0u) atomicMax(a.maxcos2, c2_lds);
+  if (chunk == 0 && tid == 0 && big_lds) *a.big_cos = 1;
   if (!any_flag) return;
   const R tol_in = R(0.5) * a.tol, neg2 = a.neg2;
   const int rounds = a.max_inner * n_in;
@@ -531,15 +527,15 @@ __global__ __launch_bounds__(ROT_THREADS) void k_jac_rotate(JacArgs<R> a) {
 }
 
 // rot_prev <- rot_cur (or all ones before the first sweep), rot_cur <- 0,
-// rot_count <- 0, maxcos2 <- 0.
-__global__ void k_jac_roll(int* rot_prev, int* rot_cur, int* rot_count, unsigned* maxcos2, int nbp, int first) {
+// rot_count <- 0, big_cos <- 0.
+__global__ void k_jac_roll(int* rot_prev, int* rot_cur, int* rot_count, int* big_cos, int nbp, int first) {
   for (int i = threadIdx.x; i < nbp; i += blockDim.x) {
     rot_prev[i] = first ? 1 : rot_cur[i];
     rot_cur[i] = 0;
   }
   if (threadIdx.x == 0) {
     *rot_count = 0;
-    *maxcos2 = 0u;
+    *big_cos = 0;
   }
 }
 
@@ -639,7 +635,7 @@ size_t jacobi_work_bytes(const JacobiPlan& pl) {
 
 template <typename R>
 static void launch_sweep(const JacobiPlan& pl, JacArgs<R> a, hipStream_t stream, bool first) {
-  hipLaunchKernelGGL(k_jac_roll, dim3(1), dim3(256), 0, stream, a.rot_prev, a.rot_cur, a.rot_count, a.maxcos2, pl.nbp,
+  hipLaunchKernelGGL(k_jac_roll, dim3(1), dim3(256), 0, stream, a.rot_prev, a.rot_cur, a.rot_count, a.big_cos, pl.nbp,
                      first ? 1 : 0);
   HIP_LAUNCH_OK();
   for (int r = 0; r < pl.nbp - 1; ++r) {
@@ -755,7 +751,7 @@ static int jacobi_run_t(const JacobiPlan& pl, typename JT<R>::C* x, void* work, 
   a.rot_prev = reinterpret_cast<int*>(w);
   a.rot_cur = a.rot_prev + pl.nbp;
   a.rot_count = rot_count_dev;
-  a.maxcos2 = reinterpret_cast<unsigned*>(rot_count_dev + 1);
+  a.big_cos = rot_count_dev + 1;
   const double u = JT<R>::u;
   a.tol = (R)(tol > 0.0 ? tol : 16.0 * u * std::sqrt((double)std::max(pl.len, 16)));
   // columns shorter than delta ||X||_F (delta = 8 u sqrt(len)) are numerically
@@ -764,6 +760,7 @@ static int jacobi_run_t(const JacobiPlan& pl, typename JT<R>::C* x, void* work, 
   // columns than its rank)
   const double delta = 8.0 * u * std::sqrt((double)pl.len);
   a.neg2 = (R)(delta * delta * std::max(fro2, 1e-300));
+  a.qtol = (R)(qstop_factor() > 0.0 ? (double)a.tol / qstop_factor() : 0.0);
   a.max_inner = pl.inner;
   bool graphs = false;
   if constexpr (std::is_same<R, double>::value) graphs = use_graphs() && pl.nbp > 4;
@@ -778,15 +775,14 @@ static int jacobi_run_t(const JacobiPlan& pl, typename JT<R>::C* x, void* work, 
     }
     HIP_OK(hipMemcpyAsync(rot_count_host, rot_count_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_OK(hipStreamSynchronize(stream));
-    float c2;
-    std::memcpy(&c2, rot_count_host + 1, sizeof(float));
+    const bool big = rot_count_host[1] != 0;
     if (debug_jacobi())
-      std::fprintf(stderr, "jacobi %dx%d sweep %d: %d pair rotations, max cos^2 %.3e\n", pl.len, pl.cnt, sweep,
-                   *rot_count_host, (double)c2);
+      std::fprintf(stderr, "jacobi %dx%d sweep %d: %d pair rotations%s\n", pl.len, pl.cnt, sweep, *rot_count_host,
+                   big ? "" : ", all entering cosines below the quadratic-stop level");
     if (*rot_count_host == 0) return sweep;
     // quadratic convergence: after a sweep whose meetings all entered with
-    // cosines below delta, the next sweep starts below ~delta^2
-    if (qstop_factor() > 0.0 && (double)c2 * qstop_factor() <= (double)a.tol) return sweep;
+    // squared cosines below tol / f, the next one starts below ~tol^2 / f^2
+    if (qstop_factor() > 0.0 && !big) return sweep;
   }
   fail(RCS_ERR_NUMERIC, "one-sided Jacobi SVD did not converge");
 }
