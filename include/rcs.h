@@ -440,9 +440,10 @@ rcs_status rcs_mlp_adam(float* w_dev, const float* grad_dev, float* m_dev, float
  * 0 shot GEMM (sampler/amplitudes), 1 Jacobi Gram, 2 Jacobi rotation,
  * 3 two-site contraction, 4 randomized range finder, 5 the other fp64
  * factorisation kernels (Gram and Cholesky preconditioner, CholeskyQR,
- * triangular inverse, projections, Newton-Schulz, ranks); class 5 times
- * every launch (its kernels differ in size, so a fixed stride could alias
- * with their launch pattern) and records no flops or bytes. */
+ * triangular inverse, projections, Newton-Schulz, ranks); classes 0 and 5
+ * time every launch (their launches differ in size in a repeating pattern,
+ * with which a fixed stride could alias); class 5 records no flops or
+ * bytes. */
 rcs_status rcs_profile_enable(int32_t every);
 /* Median event interval (seconds, host output) of back-to-back launches of
  * an empty one-workgroup kernel on the null stream, timed the same way: the

@@ -73,7 +73,11 @@ Probe::Probe(int kclass, hipStream_t s, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_every <= 0) return;
   g_tot[kclass].launches += 1;
-  const int every = kclass == kKcFactor ? 1 : g_every;
+  // the factorisation class mixes many kernels and the sampler class a
+  // periodic sequence of unequal launches (full-shot and chosen-1 GEMMs,
+  // small edge sites): a fixed stride would sample them unevenly, so every
+  // launch of these two classes is timed
+  const int every = (kclass == kKcFactor || kclass == kKcChainGemm) ? 1 : g_every;
   if ((g_counter[kclass]++ % every) != 0) return;
   if (g_pending.size() > 4096) drain(false);
   g_pending.push_back(Pending{get_event(), get_event(), kclass, flops, bytes, false});

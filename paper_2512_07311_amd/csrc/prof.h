@@ -11,7 +11,7 @@
 namespace rcs {
 
 enum KernelClass : int {
-  kKcChainGemm = 0,   // sampler / amplitude shot GEMM
+  kKcChainGemm = 0,   // sampler / amplitude shot GEMM (every launch timed)
   kKcJacGram = 1,     // Jacobi partial Grams
   kKcJacRotate = 2,   // Jacobi inner solve + block rotation
   kKcTwoSite = 3,     // two-site contraction
