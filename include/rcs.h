@@ -205,7 +205,7 @@ rcs_status rcs_sample_range(rcs_state s, uint64_t first_shot, uint64_t n_shots, 
  * that overlap on one GPU (other streams or threads) race; calls on one
  * stream are ordered and safe.  Errors: as rcs_sample_range, plus
  * INVALID_ARG when the state's maximum bond needs more than the array for a
- * 64-shot pass (bond above 16,320), DEVICE when the array's address cannot
+ * 64-shot pass (bond above 16,319), DEVICE when the array's address cannot
  * be obtained. */
 rcs_status rcs_sample_range_noalloc(rcs_state s, uint64_t first_shot, uint64_t n_shots, uint64_t seed,
                                     uint64_t* bits_dev, double* log2p_dev);
