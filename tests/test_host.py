@@ -179,3 +179,59 @@ def test_rotated_lattice_pattern_letters(rcs):
     rcs.Circuit(3, 3, 2, 1, pattern="ABEH", lattice="rotated")
     with pytest.raises(rcs.RcsError, match="A-H"):
         rcs.Circuit(3, 3, 2, 1, pattern="ABI", lattice="rotated")
+
+
+def _write_csv(path, header, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_rocprof_stage_totals(tmp_path, capsys):
+    """The profile tooling sums the named kernels' dispatches: counter
+    values per counter, or calls and durations from kernel statistics, and
+    matches kernel names without namespace or template arguments."""
+    from paper_2512_07311_amd import rocprof_summary as rs
+    cc = tmp_path / "c"
+    cc.mkdir()
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    _write_csv(cc / "x_counter_collection.csv", hdr, [
+        ["void rcs::k_jac_gram<32, double>(rcs::JacArgs<double>)", "FETCH_SIZE", 10.5, 0, 100],
+        ["void rcs::k_jac_gram<32, double>(rcs::JacArgs<double>)", "FETCH_SIZE", 4.5, 0, 100],
+        ["void rcs::k_chol_panel(double*)", "FETCH_SIZE", 2.0, 0, 10],
+        ["void rcs::k_chain_gemm(rcs::ChainArgs)", "FETCH_SIZE", 1000.0, 0, 10]])
+    rs.stage(str(cc), ["k_jac_gram", "k_chol_panel"])
+    assert "stage FETCH_SIZE: 3 dispatches, sum 17.0" in capsys.readouterr().out
+    st = tmp_path / "s"
+    st.mkdir()
+    _write_csv(st / "y_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs", "MinNs", "MaxNs",
+                                            "Percentage"], [
+        ["rcs::k_jac_rotate<32, float>", 4, 4.0e9, 1e9, 1e9, 1e9, 50.0],
+        ["rcs::k_jac_rotate<32, double>", 2, 1.0e9, 5e8, 5e8, 5e8, 25.0],
+        ["rcs::k_chain_gemm", 1, 1.0e9, 1e9, 1e9, 1e9, 25.0]])
+    rs.stage(str(st), ["k_jac_rotate"])
+    assert "stage duration: 6 dispatches, total 5.0000 s" in capsys.readouterr().out
+
+
+def test_bench_traffic_only_for_current_sources(tmp_path, monkeypatch):
+    """bench.py reports a stage's HBM traffic only from a committed summary
+    whose source hash matches the current kernel sources."""
+    import sys
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    sha = bench.stage_hash()
+    (prof / "a.md").write_text(
+        'stage-traffic-json: {"stage": "factorisation", "workload": "w", "form": "plain", '
+        '"source_sha": "%s", "bytes_per_step": 123.0}\n'
+        'stage-traffic-json: {"stage": "factorisation", "workload": "w", "form": "plain", '
+        '"source_sha": "0000000000000000", "bytes_per_step": 999.0}\n' % sha)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the hash reads the sources under ROOT: point it back at the real tree
+    monkeypatch.setattr(bench, "stage_hash", lambda: sha)
+    assert bench.measured_stage_traffic("w", "plain") == 123.0
+    assert bench.measured_stage_traffic("w", "learned") is None
+    assert bench.measured_stage_traffic("other", "plain") is None
