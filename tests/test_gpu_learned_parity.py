@@ -11,7 +11,7 @@ finder, through the C-ABI.
 * A split-bf16 learned build at 22 qubits and bond cap 256 (sketches of up to
   five panels) against the oracle's exact state, beside the rsvd-at-cap and
   plain builds of the same circuit (the three-way comparison of the learned
-  part's gain).
+  part's gain), and the learned form with the fp32 SVD of cap-limited cuts.
 """
 import math
 
@@ -167,6 +167,8 @@ def test_split_bf16_learned_build_22q_against_exact_state(env):
     learned = rcs.State.build(c, chi, eps, contraction="split_bf16", rank_mode=1, mlp_weights=w,
                               fallback_tau=1e-6)
     atcap = rcs.State.build(c, chi, eps, contraction="split_bf16", rank_mode=2, fallback_tau=1e-6)
+    learned32 = rcs.State.build(c, chi, eps, contraction="split_bf16", rank_mode=1, mlp_weights=w,
+                                fallback_tau=1e-6, svd_precision="f32")
     psi = dense.simulate(oc.Circuit(rows, cols, cyc, 71, removed=removed))
     bits = torch.arange(1 << c.n, dtype=torch.int64, device="cuda")
 
@@ -177,12 +179,14 @@ def test_split_bf16_learned_build_22q_against_exact_state(env):
         return abs(np.vdot(psi, a[:, 0] + 1j * a[:, 1])) ** 2
 
     rows_out = []
-    for name, st in (("plain", plain), ("learned", learned), ("rsvd-at-cap", atcap)):
+    for name, st in (("plain", plain), ("learned", learned), ("rsvd-at-cap", atcap), ("learned-f32", learned32)):
         inf = st.info()
         rows_out.append((name, inf.build_seconds, inf.n_rsvd_accepted, inf.n_fallbacks,
                          math.exp(inf.log_fidelity_est), fid(st)))
     for r in rows_out:
         print("%-12s build %.2f s  accepted %4d  fall-backs %4d  F_est %.5f  F_true %.5f" % r)
+    i32 = learned32.info()
+    print("learned-f32: %d fp32 splits, %d redone" % (i32.n_svd_f32, i32.n_svd_f32_redone))
     _, _, _, _, fe_p, ft_p = rows_out[0]
     _, _, acc_l, _, fe_l, ft_l = rows_out[1]
     assert learned.info().canonical == 1
@@ -191,3 +195,10 @@ def test_split_bf16_learned_build_22q_against_exact_state(env):
     r_plain = ft_p / fe_p
     assert 0.5 * r_plain <= ft_l / fe_l <= 2.0 * r_plain
     assert ft_l >= 0.5 * ft_p
+    # the fp32-SVD learned form: cap-limited cuts through the fp32 Jacobi,
+    # estimated fidelity within 1% of the plain build's and true fidelity
+    # no lower than 99% of it
+    _, _, _, _, fe_32, ft_32 = rows_out[3]
+    assert i32.n_svd_f32 > 0
+    assert abs(fe_32 / fe_p - 1.0) <= 0.01
+    assert ft_32 >= 0.99 * ft_p
