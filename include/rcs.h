@@ -182,7 +182,10 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
  * Section 3.2 stage 3: n_shots measurement shots from a right-canonical,
  * unit-norm state.  Shot i, site k (MPS order): w_s = v A_k^s, p_s = |w_s|^2
  * in fp64, u = uniform from Philox(seed; shot i, site k), bit = (u*(p0+p1)
- * >= p0), v <- w_bit.  bits_dev[i] receives the bitstring of shot
+ * >= p0), v <- w_bit.  Past the first site, where dl*dr >= 1024 and not at
+ * the last site, p0 + p1 is taken as |v|^2 (equal for a right-canonical
+ * state up to its canonical residual) and w_1 is computed only for the
+ * shots that chose 1.  bits_dev[i] receives the bitstring of shot
  * first_shot + i, log2p_dev[i] (nullable) log2 |psi(b)|^2.  Shots depend
  * only on (state, seed, shot index), so ranges computed separately and
  * concatenated equal one call.  Errors: INVALID_ARG (null bits_dev), STATE
