@@ -27,8 +27,6 @@ BuildWork* new_work();
 void delete_work(BuildWork* w);
 
 // Runs the schedule of circuit c on the freshly allocated state st.
-void build_dispatch(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps,
-                    const BuildOptions& o, BuildWork& ws);
 void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, const BuildOptions& o,
                BuildWork& ws);
 

@@ -1409,7 +1409,6 @@ void canonicalize(rcs_state_s& st, BuildWork& ws) {
 void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, const BuildOptions& o,
                BuildWork& ws) {
   upload_gates_once();
-  jacobi_init_attributes();
   RCS_REQUIRE(c.n <= 64, "too many qubits");
   st.pi = c.snake;
   std::array<double2, 16> fs, sw;
@@ -1481,11 +1480,6 @@ void build_one(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps, con
   st.build_seconds = ms * 1e-3;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-}
-
-void build_dispatch(rcs_state_s& st, const rcs_circuit_s& c, int chi, double eps,
-                    const BuildOptions& o, BuildWork& ws) {
-  build_one(st, c, chi, eps, o, ws);
 }
 
 BuildWork* new_work() { return new BuildWork(); }
@@ -1562,7 +1556,7 @@ rcs_status rcs_build_state_ex(rcs_circuit circuit, int32_t chi, double trunc_eps
   HIP_OK(hipGetDevice(&st->device));
   rcs::state_alloc(*st, circuit->n, chi);
   std::unique_ptr<rcs::BuildWork, void (*)(rcs::BuildWork*)> ws(rcs::new_work(), rcs::delete_work);
-  rcs::build_dispatch(*st, *circuit, chi, trunc_eps, b, *ws);
+  rcs::build_one(*st, *circuit, chi, trunc_eps, b, *ws);
   *out = st.release();
   RCS_API_END
 }
@@ -1810,7 +1804,9 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
     cost[i] = (double)circuits[i]->ops.size() * c * c * c;
   }
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  int n_workers = 8;
+  // as many streams as the runtime's hardware queues per process (four by
+  // default): more would share queues and serialise behind each other
+  int n_workers = 4;
   if (const char* e = std::getenv("RCS_BATCH_STREAMS")) n_workers = std::max(1, std::min(32, std::atoi(e)));
   n_workers = std::max(1, std::min(n_workers, n));
   hipEvent_t ready;
@@ -1838,7 +1834,7 @@ rcs_status rcs_build_batch(const rcs_circuit* circuits, const int32_t* chi, cons
         st->device = dev;
         try {
           rcs::state_alloc(*st, circuits[i]->n, chi[i]);
-          rcs::build_dispatch(*st, *circuits[i], chi[i], eps[i], bo, *ws);
+          rcs::build_one(*st, *circuits[i], chi[i], eps[i], bo, *ws);
           HIP_OK(hipStreamSynchronize(s));
         } catch (...) {
           // let queued work finish before the state and workspaces are freed

@@ -20,7 +20,6 @@ struct JacobiPlan {
 // jb <= 0 picks the default block width for the shape.
 JacobiPlan jacobi_plan(int len, int cnt, int jb = 0);
 size_t jacobi_work_bytes(const JacobiPlan& pl);
-void jacobi_init_attributes();
 // Orthogonalises the columns of x in place; returns the number of sweeps
 // (the last one rotates nothing, or its largest entering cosine squared is
 // below tol / 100, after which the next would rotate nothing: quadratic

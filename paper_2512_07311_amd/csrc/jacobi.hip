@@ -797,8 +797,6 @@ int jacobi_run_f32(const JacobiPlan& pl, float2* x, void* work, int* rot_count_d
   return jacobi_run_t<float>(pl, x, work, rot_count_dev, rot_count_host, fro2, stream, max_sweeps, tol);
 }
 
-void jacobi_init_attributes() {}
-
 }  // namespace rcs
 
 extern "C" {
