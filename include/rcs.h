@@ -459,7 +459,7 @@ rcs_status rcs_profile_read(int32_t kclass, int64_t* launches, int64_t* timed, d
 const char* rcs_profile_class_name(int32_t kclass);
 
 /* --------------------------------------------------------------- tuning
- * Launch parameters of the fp64 Jacobi SVD per column-count bucket: the
+ * Launch parameters of the Jacobi SVD (fp64 and fp32) per column-count bucket: the
  * first entry with cnt <= cnt_max applies (block = 16 or 32 columns per
  * block, inner_sweeps in [1, 8] two-sided sweeps per block-pair meeting).
  * Process-wide; written by the autotuner (paper_2512_07311_amd/autotune.py)
