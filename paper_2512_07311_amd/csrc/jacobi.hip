@@ -22,7 +22,10 @@
 //            matrix cores.
 // A pair whose two blocks were not rotated since the pair last met is
 // skipped (it is still orthogonal), so late sweeps cost almost nothing.  A
-// sweep that rotates nothing ends the iteration.
+// sweep that rotates nothing ends the iteration, and so does a sweep whose
+// meetings all entered with squared cosines below tol / 100 (the rotate
+// pass raises a flag otherwise): at that point convergence is quadratic and
+// the next sweep would rotate nothing.
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
