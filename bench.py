@@ -27,6 +27,7 @@ T_PROC0 = time.time()
 
 import argparse  # noqa: E402
 import json  # noqa: E402
+import math  # noqa: E402
 import os  # noqa: E402
 import sys  # noqa: E402
 
@@ -311,6 +312,16 @@ def main_batch(args, wl):
     print(json.dumps(out), flush=True)
 
 
+def learned_vs_plain(plain_build_s, plain_step_s, plain_logf, learned_build_s, learned_step_s, learned_logf):
+    """The learned form's standing against the plain form: faster in state
+    build and in the whole step (shots/s), at an estimated fidelity within
+    1% of the plain form's."""
+    rel = math.exp(learned_logf - plain_logf) - 1.0
+    return {"build_faster": learned_build_s < plain_build_s, "step_faster": learned_step_s < plain_step_s,
+            "fest_within_1pct": abs(rel) <= 0.01,
+            "met": learned_build_s < plain_build_s and learned_step_s < plain_step_s and abs(rel) <= 0.01}
+
+
 def svd_roofline(prof, inf, floor_s, steps, workload=None, form=None):
     """Roofline of the fp64 factorisation stage, every kernel that computes
     the build's SVDs and centre moves (Jacobi Gram and rotation passes, the
@@ -497,7 +508,9 @@ def main():
                 "build_speedup_vs_plain": inf.build_seconds / li.build_seconds,
                 "n_rsvd_accepted": li.n_rsvd_accepted, "n_fallbacks": li.n_fallbacks,
                 "n_svd_f32": li.n_svd_f32, "n_svd_f32_redone": li.n_svd_f32_redone,
-                "contraction": wl["precision"], "svd_precision": args.learned_svd}
+                "contraction": wl["precision"], "svd_precision": args.learned_svd,
+                "bar_vs_plain": learned_vs_plain(inf.build_seconds, sec, inf.log_fidelity_est,
+                                                 li.build_seconds, lsec, li.log_fidelity_est)}
             del lst
         else:
             out["learned"] = {"skipped": "wall-clock budget"}

@@ -235,3 +235,19 @@ def test_bench_traffic_only_for_current_sources(tmp_path, monkeypatch):
     assert bench.measured_stage_traffic("w", "plain") == 123.0
     assert bench.measured_stage_traffic("w", "learned") is None
     assert bench.measured_stage_traffic("other", "plain") is None
+
+
+def test_bench_learned_vs_plain_bar(monkeypatch):
+    """The bench line's verdict on the learned form: faster build and step
+    at an estimated fidelity within 1% of the plain form's."""
+    import math
+    import sys
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    import bench
+    lf = -29.86
+    ok = bench.learned_vs_plain(66.4, 76.6, lf, 52.3, 62.6, lf + math.log(1 - 0.0075))
+    assert ok == {"build_faster": True, "step_faster": True, "fest_within_1pct": True, "met": True}
+    far = bench.learned_vs_plain(66.4, 76.6, lf, 52.3, 62.6, lf + math.log(1 - 0.02))
+    assert far["fest_within_1pct"] is False and far["met"] is False
+    slow = bench.learned_vs_plain(66.4, 76.6, lf, 70.0, 80.0, lf)
+    assert slow["build_faster"] is False and slow["step_faster"] is False and slow["met"] is False
