@@ -230,6 +230,45 @@ def test_interleaved_network_exact_mps_equals_dense(rows, cols, cyc, seed, remov
     assert st.canonical_residual() <= 1e-12
 
 
+def test_branch_probabilities_add_to_the_prefix_norm():
+    """On a right-canonical MPS the two branch probabilities at a site add up
+    to the squared norm of the prefix vector, p0 + p1 = ||v||^2, and that
+    norm is the marginal probability of the prefix computed from the dense
+    state: the identity the GPU sampler uses to decide from W^0 alone.
+    Checked on a truncated build along random prefixes; a left-canonical
+    site breaks it."""
+    c = Circuit(4, 4, 10, seed=6)
+    st = mps.build(c, 8, 1e-12)
+    assert st.canonical_residual() <= 1e-12
+    psi = st.to_dense()
+    g = np.random.default_rng(3)
+    for _ in range(20):
+        v = np.ones(1, dtype=np.complex128)
+        prefix = []
+        for k in range(st.n):
+            w = [v @ st.A[k][:, s, :] for s in (0, 1)]
+            p = [float(np.vdot(x, x).real) for x in w]
+            assert abs(p[0] + p[1] - float(np.vdot(v, v).real)) <= 1e-12 * max(1.0, float(np.vdot(v, v).real))
+            b = int(g.random() < p[1] / (p[0] + p[1]))
+            prefix.append(b)
+            v = w[b]
+            # marginal of the prefix from the dense state (bit q = qubit q)
+            idx = np.arange(1 << st.n)
+            mask = np.ones(1 << st.n, dtype=bool)
+            for kk, bb in enumerate(prefix):
+                mask &= ((idx >> st.pi[kk]) & 1) == bb
+            marg = float(np.sum(np.abs(psi[mask]) ** 2))
+            assert abs(marg - float(np.vdot(v, v).real)) <= 1e-12
+    # the same state with its centre moved to the last site: the first
+    # sites are then left-canonical (sum_s A^s^H A^s = I), and at site 0 the
+    # branch probabilities add up to the bond dimension, not to ||v||^2 = 1
+    bad = mps.build(c, 8, 1e-12)
+    bad.move_center(bad.n - 1, bad.n - 1)
+    w0 = [bad.A[0][:, s, :].ravel() for s in (0, 1)]
+    assert abs(sum(float(np.vdot(x, x).real) for x in w0) - bad.A[0].shape[2]) < 1e-12
+    assert bad.A[0].shape[2] > 1
+
+
 def _replay_labels(circ, ops, pi0):
     """Follow the qubit labels through a schedule: the qubit pairs every
     fSim update acts on, per cycle, and the order at each layer's end."""
