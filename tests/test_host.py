@@ -251,3 +251,25 @@ def test_bench_learned_vs_plain_bar(monkeypatch):
     assert far["fest_within_1pct"] is False and far["met"] is False
     slow = bench.learned_vs_plain(66.4, 76.6, lf, 70.0, 80.0, lf)
     assert slow["build_faster"] is False and slow["step_faster"] is False and slow["met"] is False
+
+
+def test_bench_stage_roofline_arithmetic(monkeypatch):
+    """The headline roofline: nominal SVD + QR flops over the probed stage
+    time (each class's average launch time times its launches), against the
+    fp64 peak."""
+    import sys
+    import types
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    import bench
+    prof = [dict(name="k_chain_gemm", launches=10, timed=10, seconds=1.0),
+            dict(name="k_jac_gram", launches=1600, timed=100, seconds=2e-3),        # 20 us each
+            dict(name="k_jac_rotate", launches=1600, timed=100, seconds=4e-3),      # 40 us each
+            dict(name="k_factor_other", launches=50, timed=50, seconds=5e-3)]        # 100 us each
+    inf = types.SimpleNamespace(nominal_svd_flops=6.0e12, nominal_qr_flops=1.0e11)
+    r = bench.svd_roofline(prof, inf, 4e-6, 1)
+    t = 1600 * 20e-6 + 1600 * 40e-6 + 50 * 100e-6
+    assert abs(r["kernel_seconds_per_step"] - t) < 1e-12
+    assert abs(r["achieved"] - 6.1e12 / t / 1e12) < 1e-9
+    assert abs(r["frac"] - 6.1e12 / t / 78.6e12) < 1e-12
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert r["per_kernel"]["k_jac_rotate"]["launches_per_step"] == 1600
